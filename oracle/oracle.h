@@ -1,0 +1,116 @@
+/*
+ * CPU FP64 oracle for batched constant-pressure Radau IIA chemical kinetics.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This code is the independent reference that the
+ * HIP library is checked against; it shares no code, header, table or constant
+ * generator with that library.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg load it.
+ *
+ * What it computes (the paper delegates the equations to pyJac and Radau IIA
+ * to Hairer & Wanner; Sec. 2.1):
+ *   - the adiabatic constant-pressure reactor in (T, Y_1..Y_K): species source
+ *     terms from mass-action kinetics with Arrhenius forward rates, reverse
+ *     rates from NASA-7 equilibrium constants, third-body and Troe falloff
+ *     modifiers (Sec. 2.1, "constant-pressure, mass-fraction-based");
+ *   - the exact analytical Jacobian of that right-hand side;
+ *   - the 3-stage, order-5 Radau IIA method with simplified Newton, embedded
+ *     error estimate and adaptive step control, tolerances atol/rtol
+ *     (Sec. 2.1), one independent IVP per state, OpenMP over states
+ *     (Sec. 3, CPU runs).
+ * Everything is double precision; built with -ffp-contract=off.
+ */
+#ifndef RK_ORACLE_H
+#define RK_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OR_RU 8.314462618     /* J/(mol K) */
+#define OR_PATM 101325.0      /* Pa */
+
+typedef struct {
+    int kind;                 /* 0 elementary, 1 third body, 2 Troe falloff */
+    int nr, np;
+    int reac[2], prod[2];
+    double A, b, Ea;          /* forward (high-pressure limit for kind 2) */
+    double A0, b0, Ea0;       /* kind 2 low-pressure limit */
+    double troe[4];           /* a, T***, T*, T** */
+    double *eff;              /* [K] collision efficiencies (kind 1, 2), else NULL */
+} or_reaction;
+
+typedef struct {
+    int K, R, E;
+    double *W;                /* [K] kg/mol */
+    int *comp;                /* [K*E] */
+    double *Tlow, *Tmid, *Thigh;
+    double *alow, *ahigh;     /* [K*7] */
+    or_reaction *rx;          /* [R] */
+} or_mech;
+
+/* integrator status per state */
+enum { OR_OK = 0, OR_STEP_LIMIT = 1, OR_H_UNDERFLOW = 2, OR_NONFINITE = 3 };
+
+typedef struct {
+    int kmax;                 /* max Newton iterations per step (default 7) */
+    double kappa;             /* Newton stopping constant; <= 0 -> default rule */
+    double h0;                /* initial step; <= 0 -> min(dt, 1e-6 s) */
+    int nmax;                 /* step attempts limit (default 100000) */
+    int untransformed;        /* 1: solve the 3N x 3N Newton system directly */
+    int isothermal;           /* 1: dT/dt = 0 (used only to relax burnt templates) */
+} or_opts;
+
+typedef struct {
+    int32_t status;
+    int32_t nstep;            /* step attempts (Newton started) */
+    int32_t naccept, nreject, nnewton, nnewtfail, nfev, njev, nlu;
+    double h_first;           /* size of the first accepted step */
+} or_result;
+
+int  or_mech_load(const char *path, or_mech **out);
+void or_mech_free(or_mech *m);
+int  or_mech_dims(const or_mech *m, int *K, int *R, int *E);
+
+/* default options */
+void or_default_opts(or_opts *o);
+
+/* thermo of every species at T: cp/R, h/(RT), s/R  (each [K]) */
+void or_thermo(const or_mech *m, double T, double *cp, double *h, double *s);
+
+/* rates of progress q[R] and production rates wdot[K] (mol/m^3/s) at (T, Y, P) */
+void or_rates(const or_mech *m, const double *TY, double P, double *q, double *wdot);
+
+/* right-hand side f[N] of y = (T, Y_1..Y_K) at pressure P */
+void or_rhs(const or_mech *m, const double *y, double P, double *f);
+
+/* analytical Jacobian, row-major N x N: J[i*N+j] = d f_i / d y_j */
+void or_jac(const or_mech *m, const double *y, double P, double *J);
+
+/* complex-step Jacobian (step 1e-30 i on each column) */
+void or_jac_cs(const or_mech *m, const double *y, double P, double *J);
+
+/* Radau IIA constants: A[9] (row-major), c[3], b[3], gamma, alpha, beta of
+ * eig(A^-1), T[9], Tinv[9] (T^-1 A^-1 T = [[g,0,0],[0,a,-b],[0,b,a]]), d[3] */
+void or_radau_constants(double *A, double *c, double *b, double *ev, double *T, double *Tinv, double *d);
+
+/* batch integration over [0, dt]; rows are (T, Y_1..Y_K, P), row-major
+ * [n][K+2].  h0 may be NULL (per-state initial steps otherwise). */
+int or_integrate_batch(const or_mech *m, int64_t n, double dt, const double *y_in, double *y_out,
+                       double atol, double rtol, const or_opts *o, const double *h0,
+                       or_result *res, int nthreads);
+
+/* Radau IIA on the linear system y' = M y (row-major N x N), for the
+ * closed-form checks.  Accepted step sizes are written to hrec (capacity cap). */
+int or_integrate_linear(int N, const double *M, const double *y0, double dt, double atol, double rtol,
+                        const or_opts *o, double *y_out, or_result *res, double *hrec, int cap);
+
+/* One Radau step of fixed size h on the chemistry RHS with Newton iterated to
+ * convergence (no error control); used for fixed-step refinement studies. */
+int or_fixed_steps(const or_mech *m, const double *y_row, double dt, int nsteps, double *y_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
