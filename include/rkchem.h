@@ -1,0 +1,131 @@
+/*
+ * rkchem — batched constant-pressure Radau IIA chemical-kinetics integration
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * The library integrates many independent thermochemical states over one
+ * global time step, as in the paper's GPU study of stiff kinetics integrators
+ * (Curtis, Niemeyer & Sung, Sec. 2.1-2.2): each state is a constant-pressure,
+ * adiabatic, homogeneous reactor in (T, Y_1..Y_K); the integrator is the
+ * three-stage, fifth-order Radau IIA method with simplified Newton iterations
+ * on an analytical Jacobian, an embedded error estimate and adaptive step
+ * control under absolute/relative tolerances (Sec. 2.1).  One call integrates
+ * every state from t = 0 to t = dt.
+ *
+ * All compute runs in the library's HIP kernels on the current HIP device.
+ * Pointers named `d_*` are device pointers the caller owns (e.g. from torch);
+ * the library owns mechanism handles and its internal workspaces.
+ *
+ * Error handling: functions return 0 on success or a negative RK_E* code; the
+ * message of the last failing call on the calling thread is returned by
+ * rk_last_error().  Per-state integration failures are not errors: they are
+ * reported as status codes through stats_get().
+ */
+#ifndef RKCHEM_H
+#define RKCHEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define RK_OK 0
+#define RK_EIO (-1)      /* mechanism file cannot be opened */
+#define RK_EPARSE (-2)   /* mechanism file malformed */
+#define RK_EINVAL (-3)   /* invalid argument or mechanism that fails validation */
+#define RK_EHIP (-4)     /* HIP runtime error */
+#define RK_ENOMEM (-5)   /* device allocation failed */
+
+/* per-state status codes */
+#define RK_ST_OK 0           /* reached t = dt */
+#define RK_ST_STEP_LIMIT 1   /* more step attempts than the limit (option nmax) */
+#define RK_ST_H_UNDERFLOW 2  /* step size fell below 1e-14 dt */
+#define RK_ST_NONFINITE 3    /* input state not finite, T <= 0 or P <= 0; y_out = y_in */
+
+typedef struct rk_mech rk_mech;
+
+/* Statistics of the last radau_integrate call on a handle. */
+typedef struct rk_stats {
+    int64_t n_states;
+    int64_t steps;            /* step attempts (Newton started), summed over states */
+    int64_t accepted, rejected;
+    int64_t newton_iters, newton_fail;
+    int64_t f_evals, jac_evals, lu_factor;
+    int64_t n_failed;         /* states whose status is not RK_ST_OK */
+    int32_t max_steps, min_steps;
+    /* divergence D = 1 - sum_i d_i / (w max_i d_i) over groups of w consecutive
+     * states (d_i = step attempts of state i), the paper's Eq. (3); histogram
+     * of D in 20 bins of width 0.05, for w = 64 (one wavefront) and w = 32 */
+    int64_t d_hist64[20];
+    int64_t d_hist32[20];
+    double d_mean64, d_mean32;
+    double kernel_ms;         /* device time of the last call (HIP events) */
+} rk_stats;
+
+/* mech_load — read a mechanism file and upload it to the current device.
+ *   path: text mechanism (species with element counts and molar masses,
+ *         two-range NASA-7 thermodynamics, reversible reactions with 1-2
+ *         species per side: elementary, third-body, Troe falloff; SI units).
+ *   out:  receives a handle owned by the library; release with mech_free.
+ * Validates element balance of every reaction, NASA-7 continuity of cp, h, s
+ * at T_mid (relative 1e-6) and positive molar masses.
+ * Returns RK_OK, RK_EIO, RK_EPARSE, RK_EINVAL or RK_EHIP/RK_ENOMEM. */
+int mech_load(const char *path, rk_mech **out);
+
+/* mech_free — release a handle and its device memory (NULL is a no-op).
+ * Synchronises the handle's last stream first. */
+void mech_free(rk_mech *mech);
+
+/* mech_dims — number of species K and reactions R of a handle. */
+int mech_dims(const rk_mech *mech, int32_t *K, int32_t *R);
+
+/* radau_integrate — integrate n_states independent states over [0, dt].
+ *   d_y_in, d_y_out: device arrays of (K+2)*n_states doubles, component-major
+ *       (struct of arrays): element (c, i) at c*n_states + i, c = 0 temperature
+ *       [K], c = 1..K mass fractions Y_k, c = K+1 pressure [Pa].  Pressure is
+ *       copied through unchanged.  d_y_out may equal d_y_in.
+ *   atol, rtol: tolerances of the error and Newton norms (paper: 1e-10, 1e-6).
+ *   stream: hipStream_t to enqueue on (NULL = default stream).  The call
+ *       returns after enqueueing; results are ready when the stream is.
+ * One call in flight per handle: a second call on the same handle must not
+ * start before the first one's stream work has been ordered before it.
+ * Returns RK_EINVAL for dt <= 0, atol < 0, rtol <= 0, n_states < 0 or a NULL
+ * pointer with n_states > 0; RK_ENOMEM / RK_EHIP on runtime failures.
+ * Failures of individual states go to their status (stats_get); a failed
+ * state keeps its last accepted solution in d_y_out. */
+int radau_integrate(rk_mech *mech, int64_t n_states, double dt, const double *d_y_in, double *d_y_out,
+                    double atol, double rtol, void *stream);
+
+/* stats_get — statistics of the last radau_integrate on this handle.
+ * Synchronises that call's stream.  per_state_steps and per_state_status are
+ * optional HOST arrays of n_states int32 (step attempts, status code). */
+int stats_get(rk_mech *mech, rk_stats *out, int32_t *per_state_steps, int32_t *per_state_status);
+
+/* radau_set_option — integrator options of a handle (strings):
+ *   "variant"  "lane" (default; one lane per state, the paper's per-thread
+ *              pattern) | "wave" (one wavefront cooperates on a state)
+ *   "kmax"     max Newton iterations per step (default 7)
+ *   "kappa"    Newton stopping constant (default max(10u/rtol, min(0.03, rtol^0.5)))
+ *   "nmax"     step-attempt limit per state (default 100000)
+ *   "h0"       initial step size in seconds (default min(dt, 1e-6))
+ * Returns RK_EINVAL for an unknown key or a malformed value. */
+int radau_set_option(rk_mech *mech, const char *key, const char *value);
+
+/* rk_last_error — message of the last failing call on this thread ("" if none). */
+const char *rk_last_error(void);
+
+/* ---- kernel-level entry points used by the parity tests ------------------ */
+
+/* rk_dbg_rhs — source terms f(y) for n states: d_y as in radau_integrate,
+ * d_f receives (K+1)*n doubles, component-major (dT/dt, dY_k/dt). */
+int rk_dbg_rhs(rk_mech *mech, int64_t n, const double *d_y, double *d_f, void *stream);
+
+/* rk_dbg_jacobian — analytical Jacobian for n states: d_J receives
+ * (K+1)^2 * n doubles, element (r, c) of state i at (r*(K+1) + c)*n + i. */
+int rk_dbg_jacobian(rk_mech *mech, int64_t n, const double *d_y, double *d_J, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -66,6 +66,7 @@ def lib():
         L.or_mech_dims.argtypes = [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_int)] * 3
         L.or_thermo.argtypes = [ctypes.c_void_p, ctypes.c_double, dp, dp, dp]
         L.or_rates.argtypes = [ctypes.c_void_p, dp, ctypes.c_double, dp, dp]
+        L.or_rates2.argtypes = [ctypes.c_void_p, dp, ctypes.c_double, dp, dp, dp, dp]
         L.or_rhs.argtypes = [ctypes.c_void_p, dp, ctypes.c_double, dp]
         L.or_rhs_iso.argtypes = [ctypes.c_void_p, dp, ctypes.c_double, dp]
         L.or_jac.argtypes = [ctypes.c_void_p, dp, ctypes.c_double, dp]
@@ -125,6 +126,13 @@ class Mech:
         q, w = np.zeros(self.R), np.zeros(self.K)
         lib().or_rates(self.h, _p(y), P, _p(q), _p(w))
         return q, w
+
+    def rates_fr(self, y: np.ndarray, P: float):
+        """(q, wdot, forward part, reverse part) with q = qf - qr."""
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        q, w, qf, qr = np.zeros(self.R), np.zeros(self.K), np.zeros(self.R), np.zeros(self.R)
+        lib().or_rates2(self.h, _p(y), P, _p(q), _p(w), _p(qf), _p(qr))
+        return q, w, qf, qr
 
     def rhs(self, y: np.ndarray, P: float, isothermal: bool = False) -> np.ndarray:
         y = np.ascontiguousarray(y, dtype=np.float64)

@@ -45,7 +45,8 @@
 
 void or_thermo(const or_mech *m, double T, double *cp, double *h, double *s) { thermo_r(m, T, cp, h, s); }
 
-void or_rates(const or_mech *m, const double *TY, double P, double *q, double *wdot) {
+/* forward and reverse parts of each rate of progress (q = qf - qr), optional */
+void or_rates2(const or_mech *m, const double *TY, double P, double *q, double *wdot, double *qf, double *qr) {
     const int K = m->K;
     double *C = malloc(sizeof(double) * 4 * K);
     double *cp = C + K, *h = cp + K, *s = h + K;
@@ -53,8 +54,12 @@ void or_rates(const or_mech *m, const double *TY, double P, double *q, double *w
     for (int k = 0; k < K; ++k) sumYW += TY[1 + k] / m->W[k];
     double rho = P / sumYW / (OR_RU * T);
     for (int k = 0; k < K; ++k) C[k] = rho * TY[1 + k] / m->W[k];
-    kinetics_r(m, T, C, q, wdot, cp, h, s);
+    kinetics_r(m, T, C, q, wdot, cp, h, s, qf, qr);
     free(C);
+}
+
+void or_rates(const or_mech *m, const double *TY, double P, double *q, double *wdot) {
+    or_rates2(m, TY, P, q, wdot, NULL, NULL);
 }
 
 void or_rhs(const or_mech *m, const double *y, double P, double *f) { rhs_r(m, y, P, f, 0); }

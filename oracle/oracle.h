@@ -81,6 +81,8 @@ void or_thermo(const or_mech *m, double T, double *cp, double *h, double *s);
 
 /* rates of progress q[R] and production rates wdot[K] (mol/m^3/s) at (T, Y, P) */
 void or_rates(const or_mech *m, const double *TY, double P, double *q, double *wdot);
+/* as or_rates, also returning the forward and reverse parts qf, qr (q = qf - qr) */
+void or_rates2(const or_mech *m, const double *TY, double P, double *q, double *wdot, double *qf, double *qr);
 
 /* right-hand side f[N] of y = (T, Y_1..Y_K) at pressure P */
 void or_rhs(const or_mech *m, const double *y, double P, double *f);

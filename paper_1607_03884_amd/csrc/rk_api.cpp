@@ -1,0 +1,536 @@
+// Host side of the rkchem C ABI: mechanism reader and validation, device
+// upload, Radau IIA constants, workspace management, statistics.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "rk_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(RK_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// ---- tokenizer ----------------------------------------------------------------
+struct Tokens {
+    std::vector<std::string> t;
+    size_t i = 0;
+    bool bad = false;
+    std::string next() {
+        if (i >= t.size()) { bad = true; return ""; }
+        return t[i++];
+    }
+    double num() {
+        std::string s = next();
+        if (bad) return 0.0;
+        char *e = nullptr;
+        double v = std::strtod(s.c_str(), &e);
+        if (e == s.c_str() || *e) bad = true;
+        return v;
+    }
+    int integer() {
+        std::string s = next();
+        if (bad) return 0;
+        char *e = nullptr;
+        long v = std::strtol(s.c_str(), &e, 10);
+        if (e == s.c_str() || *e) bad = true;
+        return (int)v;
+    }
+    void word(const char *w) {
+        if (next() != w) bad = true;
+    }
+};
+
+// ---- NASA-7 on the host (validation only) --------------------------------------
+void nasa7(const double *a, double T, double &cp, double &h, double &s) {
+    cp = a[0] + T * (a[1] + T * (a[2] + T * (a[3] + T * a[4])));
+    h = a[0] + T * (a[1] / 2 + T * (a[2] / 3 + T * (a[3] / 4 + T * a[4] / 5))) + a[5] / T;
+    s = a[0] * std::log(T) + T * (a[1] + T * (a[2] / 2 + T * (a[3] / 3 + T * a[4] / 4))) + a[6];
+}
+
+struct Rx {
+    int kind, nr, np, r[2], p[2];
+    double A, b, Ea, A0 = 0, b0 = 0, Ea0 = 0, troe[4] = {0, 0, 0, 0};
+    std::vector<double> eff;
+};
+
+int parse(const char *path, rk_mech *m, std::vector<Rx> &rx, std::vector<double> &alo, std::vector<double> &ahi) {
+    std::ifstream in(path);
+    if (!in) return fail(RK_EIO, std::string("cannot open mechanism file ") + path);
+    Tokens tk;
+    std::string line;
+    while (std::getline(in, line)) {
+        const size_t hash = line.find('#');
+        if (hash != std::string::npos) line.resize(hash);
+        std::istringstream ls(line);
+        std::string w;
+        while (ls >> w) tk.t.push_back(w);
+    }
+    tk.word("rkmech");
+    if (tk.integer() != 1) tk.bad = true;
+    tk.word("name");
+    m->name = tk.next();
+    tk.word("elements");
+    m->E = tk.integer();
+    for (int e = 0; e < m->E && !tk.bad; ++e) tk.next();
+    tk.word("species");
+    m->K = tk.integer();
+    if (tk.bad || m->K <= 0 || m->E <= 0 || m->K > 4096) return fail(RK_EPARSE, "bad header in mechanism file");
+    const int K = m->K;
+    m->W.assign(K, 0.0);
+    m->comp.assign((size_t)K * m->E, 0);
+    m->Tmid.assign(K, 0.0);
+    alo.assign((size_t)K * 7, 0.0);
+    ahi.assign((size_t)K * 7, 0.0);
+    for (int k = 0; k < K && !tk.bad; ++k) {
+        tk.next();
+        m->W[k] = tk.num();
+        for (int e = 0; e < m->E; ++e) m->comp[(size_t)k * m->E + e] = tk.integer();
+    }
+    tk.word("thermo");
+    std::vector<int> seen(K, 0);
+    for (int i = 0; i < K && !tk.bad; ++i) {
+        const int k = tk.integer();
+        if (k < 0 || k >= K) { tk.bad = true; break; }
+        seen[k] = 1;
+        tk.num();                 // T_low (not used: polynomials are evaluated as they are)
+        m->Tmid[k] = tk.num();
+        tk.num();                 // T_high
+        for (int a = 0; a < 7; ++a) alo[(size_t)k * 7 + a] = tk.num();
+        for (int a = 0; a < 7; ++a) ahi[(size_t)k * 7 + a] = tk.num();
+    }
+    tk.word("reactions");
+    m->R = tk.integer();
+    if (tk.bad || m->R < 0) return fail(RK_EPARSE, "bad species/thermo section in mechanism file");
+    rx.resize(m->R);
+    for (int j = 0; j < m->R && !tk.bad; ++j) {
+        Rx &x = rx[j];
+        x.kind = tk.integer();
+        x.nr = tk.integer();
+        if (x.nr < 1 || x.nr > 2) { tk.bad = true; break; }
+        for (int s = 0; s < x.nr; ++s) x.r[s] = tk.integer();
+        x.np = tk.integer();
+        if (x.np < 1 || x.np > 2) { tk.bad = true; break; }
+        for (int s = 0; s < x.np; ++s) x.p[s] = tk.integer();
+        x.A = tk.num(); x.b = tk.num(); x.Ea = tk.num();
+        if (x.kind == 2) {
+            x.A0 = tk.num(); x.b0 = tk.num(); x.Ea0 = tk.num();
+            for (double &v : x.troe) v = tk.num();
+        }
+        if (x.kind == 1 || x.kind == 2) {
+            x.eff.assign(K, 1.0);
+            const int ne = tk.integer();
+            for (int t = 0; t < ne && !tk.bad; ++t) {
+                const int k = tk.integer();
+                const double a = tk.num();
+                if (k < 0 || k >= K) { tk.bad = true; break; }
+                x.eff[k] = a;
+            }
+        } else if (x.kind != 0) {
+            tk.bad = true;
+        }
+        for (int s = 0; s < x.nr; ++s) if (x.r[s] < 0 || x.r[s] >= K) tk.bad = true;
+        for (int s = 0; s < x.np; ++s) if (x.p[s] < 0 || x.p[s] >= K) tk.bad = true;
+    }
+    tk.word("end");
+    if (tk.bad) return fail(RK_EPARSE, "malformed reaction section in mechanism file");
+    for (int k = 0; k < K; ++k)
+        if (!seen[k]) return fail(RK_EPARSE, "species without thermodynamic data");
+    return RK_OK;
+}
+
+int validate(const rk_mech *m, const std::vector<Rx> &rx, const std::vector<double> &alo, const std::vector<double> &ahi) {
+    for (int k = 0; k < m->K; ++k) {
+        if (!(m->W[k] > 0.0)) return fail(RK_EINVAL, "non-positive molar mass");
+        double c1, h1, s1, c2, h2, s2;
+        nasa7(&alo[(size_t)k * 7], m->Tmid[k], c1, h1, s1);
+        nasa7(&ahi[(size_t)k * 7], m->Tmid[k], c2, h2, s2);
+        auto close = [](double a, double b) { return std::fabs(a - b) <= 1e-6 * std::max(1.0, std::max(std::fabs(a), std::fabs(b))); };
+        if (!close(c1, c2) || !close(h1, h2) || !close(s1, s2))
+            return fail(RK_EINVAL, "NASA-7 polynomials discontinuous at T_mid for species " + std::to_string(k));
+    }
+    for (int j = 0; j < m->R; ++j) {
+        for (int e = 0; e < m->E; ++e) {
+            int bal = 0;
+            for (int s = 0; s < rx[j].nr; ++s) bal -= m->comp[(size_t)rx[j].r[s] * m->E + e];
+            for (int s = 0; s < rx[j].np; ++s) bal += m->comp[(size_t)rx[j].p[s] * m->E + e];
+            if (bal != 0) return fail(RK_EINVAL, "reaction " + std::to_string(j) + " is not element balanced");
+        }
+        if (!(rx[j].A > 0.0) || (rx[j].kind == 2 && !(rx[j].A0 > 0.0)))
+            return fail(RK_EINVAL, "non-positive pre-exponential factor in reaction " + std::to_string(j));
+    }
+    return RK_OK;
+}
+
+int upload(rk_mech *m, const std::vector<Rx> &rx, const std::vector<double> &alo, const std::vector<double> &ahi) {
+    const int K = m->K, R = m->R;
+    // thermo table: per species and range 16 doubles (cp, h, s polynomial coefficients)
+    m->thermo.assign((size_t)K * 32, 0.0);
+    for (int k = 0; k < K; ++k)
+        for (int r = 0; r < 2; ++r) {
+            const double *a = (r == 0 ? &alo[(size_t)k * 7] : &ahi[(size_t)k * 7]);
+            double *t = &m->thermo[(size_t)k * 32 + r * 16];
+            for (int i = 0; i < 5; ++i) t[i] = a[i];
+            for (int i = 0; i < 5; ++i) t[5 + i] = a[i] / (i + 1);
+            t[10] = a[5];
+            for (int i = 1; i < 5; ++i) t[10 + i] = a[i] / i;
+            t[15] = a[6];
+        }
+    m->rsp.assign(R, int4{-1, -1, -1, -1});
+    m->rinfo.assign(R, 0);
+    m->rpar.assign((size_t)R * rk::P_NPAR, 0.0);
+    m->eff.clear();
+    m->n3b = 0;
+    for (int j = 0; j < R; ++j) {
+        const Rx &x = rx[j];
+        m->rsp[j] = int4{x.r[0], x.nr > 1 ? x.r[1] : -1, x.p[0], x.np > 1 ? x.p[1] : -1};
+        int info = x.kind | (x.nr << 4) | (x.np << 8);
+        if (x.kind != 0) {
+            info |= (m->n3b + 1) << 12;
+            m->eff.insert(m->eff.end(), x.eff.begin(), x.eff.end());
+            ++m->n3b;
+        }
+        m->rinfo[j] = info;
+        double *p = &m->rpar[(size_t)j * rk::P_NPAR];
+        p[rk::P_A] = x.A; p[rk::P_B] = x.b; p[rk::P_EAR] = x.Ea / rk::kRu;
+        p[rk::P_A0] = x.A0; p[rk::P_B0] = x.b0; p[rk::P_EA0R] = x.Ea0 / rk::kRu;
+        p[rk::P_TA] = x.troe[0]; p[rk::P_T3] = x.troe[1]; p[rk::P_T1] = x.troe[2]; p[rk::P_T2] = x.troe[3];
+        p[rk::P_DNU] = (double)(x.np - x.nr);
+    }
+    if (m->eff.empty()) m->eff.push_back(0.0);
+    std::vector<double> invW(K);
+    for (int k = 0; k < K; ++k) invW[k] = 1.0 / m->W[k];
+
+    // one device block, each table 256-byte aligned
+    struct Part { const void *src; size_t bytes; size_t off; };
+    std::vector<Part> parts = {
+        {m->W.data(), K * sizeof(double), 0}, {invW.data(), K * sizeof(double), 0},
+        {m->Tmid.data(), K * sizeof(double), 0}, {m->thermo.data(), m->thermo.size() * sizeof(double), 0},
+        {m->rsp.data(), std::max(R, 1) * sizeof(int4), 0}, {m->rinfo.data(), std::max(R, 1) * sizeof(int), 0},
+        {m->rpar.data(), std::max<size_t>(m->rpar.size(), 1) * sizeof(double), 0},
+        {m->eff.data(), m->eff.size() * sizeof(double), 0}};
+    size_t total = 0;
+    for (Part &p : parts) { p.off = total; total += (p.bytes + 255) / 256 * 256; }
+    std::vector<char> host(total, 0);
+    for (Part &p : parts) if (p.src && p.bytes) std::memcpy(host.data() + p.off, p.src, p.bytes);
+    hipError_t e = hipGetDevice(&m->device);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    e = hipMalloc(&m->dev_block, total);
+    if (e != hipSuccess) return fail(RK_ENOMEM, "hipMalloc of mechanism tables failed");
+    e = hipMemcpy(m->dev_block, host.data(), total, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy of mechanism tables");
+    char *b = static_cast<char *>(m->dev_block);
+    rk::DevMech &d = m->dev;
+    d.K = K; d.R = R; d.N = K + 1; d.n3b = m->n3b;
+    d.W = reinterpret_cast<const double *>(b + parts[0].off);
+    d.invW = reinterpret_cast<const double *>(b + parts[1].off);
+    d.Tmid = reinterpret_cast<const double *>(b + parts[2].off);
+    d.thermo = reinterpret_cast<const double *>(b + parts[3].off);
+    d.rsp = reinterpret_cast<const int4 *>(b + parts[4].off);
+    d.rinfo = reinterpret_cast<const int *>(b + parts[5].off);
+    d.rpar = reinterpret_cast<const double *>(b + parts[6].off);
+    d.eff = reinterpret_cast<const double *>(b + parts[7].off);
+    e = hipEventCreate(&m->ev0);
+    if (e == hipSuccess) e = hipEventCreate(&m->ev1);
+    if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    return RK_OK;
+}
+
+// ---- Radau IIA constants (three-stage, order five) ------------------------------
+// A^-1 has one real eigenvalue g and a complex pair a +- i b.  T is built from
+// an eigenvector for g and the real and imaginary parts of an eigenvector for
+// a - i b, each normalised to last component 1, which gives
+// T^-1 A^-1 T = [[g,0,0],[0,a,-b],[0,b,a]].
+template <class S>
+void null_vec_last1(const S B[3][3], S v[3]) {
+    // rows 0 and 1 of B v = 0 with v2 = 1 (Cramer's rule)
+    const S det = B[0][0] * B[1][1] - B[0][1] * B[1][0];
+    v[0] = (-B[0][2] * B[1][1] + B[0][1] * B[1][2]) / det;
+    v[1] = (-B[0][0] * B[1][2] + B[1][0] * B[0][2]) / det;
+    v[2] = S(1.0);
+}
+
+void invert3(const double A[9], double R[9]) {
+    // Gauss-Jordan with partial pivoting
+    double a[3][6];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 6; ++j) a[i][j] = j < 3 ? A[i * 3 + j] : (j - 3 == i ? 1.0 : 0.0);
+    for (int c = 0; c < 3; ++c) {
+        int p = c;
+        for (int i = c + 1; i < 3; ++i) if (std::fabs(a[i][c]) > std::fabs(a[p][c])) p = i;
+        for (int j = 0; j < 6; ++j) std::swap(a[c][j], a[p][j]);
+        const double d = a[c][c];
+        for (int j = 0; j < 6; ++j) a[c][j] /= d;
+        for (int i = 0; i < 3; ++i)
+            if (i != c) {
+                const double f = a[i][c];
+                for (int j = 0; j < 6; ++j) a[i][j] -= f * a[c][j];
+            }
+    }
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) R[i * 3 + j] = a[i][j + 3];
+}
+
+void radau_constants(rk::RadauParams &p) {
+    const double r6 = std::sqrt(6.0);
+    const double A[9] = {(88.0 - 7.0 * r6) / 360.0, (296.0 - 169.0 * r6) / 1800.0, (-2.0 + 3.0 * r6) / 225.0,
+                         (296.0 + 169.0 * r6) / 1800.0, (88.0 + 7.0 * r6) / 360.0, (-2.0 - 3.0 * r6) / 225.0,
+                         (16.0 - r6) / 36.0, (16.0 + r6) / 36.0, 1.0 / 9.0};
+    p.c1 = (4.0 - r6) / 10.0;
+    p.c2 = (4.0 + r6) / 10.0;
+    const double q81 = std::cbrt(81.0), q9 = std::cbrt(9.0);
+    p.g = 30.0 / (6.0 + q81 - q9);
+    const double al = (12.0 - q81 + q9) / 60.0, be = (q81 + q9) * std::sqrt(3.0) / 60.0;
+    p.a = al / (al * al + be * be);
+    p.b = be / (al * al + be * be);
+    double Ai[9];
+    invert3(A, Ai);
+    double Br[3][3];
+    std::complex<double> Bc[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            Br[i][j] = Ai[i * 3 + j] - (i == j ? p.g : 0.0);
+            Bc[i][j] = Ai[i * 3 + j] - (i == j ? std::complex<double>(p.a, -p.b) : 0.0);
+        }
+    double v1[3];
+    std::complex<double> v2[3];
+    null_vec_last1(Br, v1);
+    null_vec_last1(Bc, v2);
+    for (int i = 0; i < 3; ++i) {
+        p.T[i * 3 + 0] = v1[i];
+        p.T[i * 3 + 1] = v2[i].real();
+        p.T[i * 3 + 2] = v2[i].imag();
+    }
+    invert3(p.T, p.Ti);
+    p.d[0] = -(13.0 + 7.0 * r6) / 3.0;
+    p.d[1] = (-13.0 + 7.0 * r6) / 3.0;
+    p.d[2] = -1.0 / 3.0;
+}
+
+bool is_device_ptr(const void *ptr) {
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, ptr) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+int ensure_workspace(rk_mech *m, int64_t n) {
+    const size_t need = rk::lane_scratch_doubles(m->K, n);
+    if (need > m->scratch_cap) {
+        if (m->scratch) { (void)hipDeviceSynchronize(); (void)hipFree(m->scratch); m->scratch = nullptr; m->scratch_cap = 0; }
+        if (hipMalloc(&m->scratch, need * sizeof(double)) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(RK_ENOMEM, "cannot allocate integrator workspace");
+        }
+        m->scratch_cap = need;
+    }
+    if (n > m->counters_cap) {
+        if (m->counters) { (void)hipDeviceSynchronize(); (void)hipFree(m->counters); m->counters = nullptr; m->counters_cap = 0; }
+        if (hipMalloc(&m->counters, (size_t)n * rk::kNumCounters * sizeof(int32_t)) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(RK_ENOMEM, "cannot allocate per-state counters");
+        }
+        m->counters_cap = n;
+    }
+    return RK_OK;
+}
+
+}  // namespace
+
+// =============================================================================
+// C ABI
+// =============================================================================
+extern "C" {
+
+const char *rk_last_error(void) { return g_err.c_str(); }
+
+int mech_load(const char *path, rk_mech **out) {
+    if (!out || !path) return fail(RK_EINVAL, "mech_load: NULL argument");
+    *out = nullptr;
+    rk_mech *m = new rk_mech();
+    std::vector<Rx> rx;
+    std::vector<double> alo, ahi;
+    int rc = parse(path, m, rx, alo, ahi);
+    if (rc == RK_OK) rc = validate(m, rx, alo, ahi);
+    if (rc == RK_OK) rc = upload(m, rx, alo, ahi);
+    if (rc != RK_OK) {
+        mech_free(m);
+        return rc;
+    }
+    *out = m;
+    g_err.clear();
+    return RK_OK;
+}
+
+void mech_free(rk_mech *m) {
+    if (!m) return;
+    if (m->have_run && m->last_stream) (void)hipStreamSynchronize(m->last_stream);
+    if (m->have_run) (void)hipDeviceSynchronize();
+    if (m->dev_block) (void)hipFree(m->dev_block);
+    if (m->scratch) (void)hipFree(m->scratch);
+    if (m->counters) (void)hipFree(m->counters);
+    if (m->ev0) (void)hipEventDestroy(m->ev0);
+    if (m->ev1) (void)hipEventDestroy(m->ev1);
+    delete m;
+}
+
+int mech_dims(const rk_mech *m, int32_t *K, int32_t *R) {
+    if (!m || !K || !R) return fail(RK_EINVAL, "mech_dims: NULL argument");
+    *K = m->K;
+    *R = m->R;
+    return RK_OK;
+}
+
+int radau_set_option(rk_mech *m, const char *key, const char *value) {
+    if (!m || !key || !value) return fail(RK_EINVAL, "radau_set_option: NULL argument");
+    std::string k(key), v(value);
+    char *e = nullptr;
+    if (k == "variant") {
+        if (v == "lane") m->variant = 0;
+        else if (v == "wave") m->variant = 1;
+        else return fail(RK_EINVAL, "unknown variant " + v);
+        return RK_OK;
+    }
+    if (k == "kmax" || k == "nmax") {
+        const long x = std::strtol(value, &e, 10);
+        if (e == value || *e || x < 1 || x > 100000000) return fail(RK_EINVAL, "bad integer for " + k);
+        (k == "kmax" ? m->kmax : m->nmax) = (int)x;
+        return RK_OK;
+    }
+    if (k == "kappa" || k == "h0") {
+        const double x = std::strtod(value, &e);
+        if (e == value || *e || !(x >= 0.0) || !std::isfinite(x)) return fail(RK_EINVAL, "bad number for " + k);
+        (k == "kappa" ? m->kappa : m->h0) = x;
+        return RK_OK;
+    }
+    return fail(RK_EINVAL, "unknown option " + k);
+}
+
+int radau_integrate(rk_mech *m, int64_t n, double dt, const double *yin, double *yout, double atol, double rtol,
+                    void *stream) {
+    if (!m) return fail(RK_EINVAL, "radau_integrate: NULL handle");
+    if (n < 0 || !(dt > 0.0) || !std::isfinite(dt) || !(atol >= 0.0) || !(rtol > 0.0))
+        return fail(RK_EINVAL, "radau_integrate: need n >= 0, dt > 0, atol >= 0, rtol > 0");
+    if (n > 0 && (!yin || !yout)) return fail(RK_EINVAL, "radau_integrate: NULL state pointer");
+    if (n > 0 && (!is_device_ptr(yin) || !is_device_ptr(yout)))
+        return fail(RK_EINVAL, "radau_integrate: state arrays must be device memory");
+    if (m->variant != 0) return fail(RK_EINVAL, "radau_integrate: variant not available in this build");
+    int rc = ensure_workspace(m, std::max<int64_t>(n, 1));
+    if (rc != RK_OK) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    rk::RadauParams p{};
+    radau_constants(p);
+    p.dt = dt;
+    p.atol = atol;
+    p.rtol = rtol;
+    p.kmax = m->kmax;
+    p.nmax = m->nmax;
+    p.kappa = m->kappa > 0.0 ? m->kappa : std::max(10.0 * 2.220446049250313e-16 / rtol, std::min(0.03, std::sqrt(rtol)));
+    p.h0 = m->h0 > 0.0 ? m->h0 : std::min(dt, 1e-6);
+    p.hmin = 1e-14 * dt;
+    hipError_t e = hipEventRecord(m->ev0, st);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    e = rk::launch_radau_lane(m->dev, p, n, yin, yout, m->scratch, m->counters, st);
+    if (e != hipSuccess) return hip_fail(e, "radau kernel launch");
+    e = hipEventRecord(m->ev1, st);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    m->last_n = n;
+    m->last_stream = st;
+    m->have_run = true;
+    return RK_OK;
+}
+
+int stats_get(rk_mech *m, rk_stats *out, int32_t *steps, int32_t *status) {
+    if (!m || !out) return fail(RK_EINVAL, "stats_get: NULL argument");
+    std::memset(out, 0, sizeof *out);
+    if (!m->have_run) return RK_OK;
+    hipError_t e = hipEventSynchronize(m->ev1);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, m->ev0, m->ev1) == hipSuccess) out->kernel_ms = ms;
+    const int64_t n = m->last_n;
+    out->n_states = n;
+    if (n == 0) return RK_OK;
+    std::vector<int32_t> c((size_t)n * rk::kNumCounters);
+    e = hipMemcpy(c.data(), m->counters, c.size() * sizeof(int32_t), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy of counters");
+    const int32_t *st = &c[(size_t)rk::C_STATUS * n], *ns = &c[(size_t)rk::C_NSTEP * n];
+    out->max_steps = 0;
+    out->min_steps = ns[0];
+    for (int64_t i = 0; i < n; ++i) {
+        out->steps += ns[i];
+        out->accepted += c[(size_t)rk::C_NACC * n + i];
+        out->rejected += c[(size_t)rk::C_NREJ * n + i];
+        out->newton_iters += c[(size_t)rk::C_NNEWT * n + i];
+        out->newton_fail += c[(size_t)rk::C_NNFAIL * n + i];
+        out->f_evals += c[(size_t)rk::C_NFEV * n + i];
+        out->jac_evals += c[(size_t)rk::C_NJEV * n + i];
+        out->lu_factor += c[(size_t)rk::C_NLU * n + i];
+        out->n_failed += st[i] != RK_ST_OK;
+        out->max_steps = std::max(out->max_steps, ns[i]);
+        out->min_steps = std::min(out->min_steps, ns[i]);
+    }
+    // divergence measure over groups of w consecutive states
+    auto hist = [&](int w, int64_t *h, double *mean) {
+        int64_t groups = 0;
+        double sum = 0.0;
+        for (int64_t g0 = 0; g0 < n; g0 += w) {
+            const int64_t g1 = std::min<int64_t>(n, g0 + w);
+            int64_t tot = 0;
+            int32_t mx = 0;
+            for (int64_t i = g0; i < g1; ++i) { tot += ns[i]; mx = std::max(mx, ns[i]); }
+            const double D = mx > 0 ? 1.0 - (double)tot / ((double)(g1 - g0) * mx) : 0.0;
+            int b = (int)(D / 0.05);
+            b = std::min(19, std::max(0, b));
+            ++h[b];
+            sum += D;
+            ++groups;
+        }
+        *mean = groups ? sum / groups : 0.0;
+    };
+    hist(64, out->d_hist64, &out->d_mean64);
+    hist(32, out->d_hist32, &out->d_mean32);
+    if (steps) std::memcpy(steps, ns, (size_t)n * sizeof(int32_t));
+    if (status) std::memcpy(status, st, (size_t)n * sizeof(int32_t));
+    return RK_OK;
+}
+
+static int dbg_common(rk_mech *m, int64_t n, const void *a, const void *b) {
+    if (!m) return fail(RK_EINVAL, "NULL handle");
+    if (n < 0) return fail(RK_EINVAL, "n < 0");
+    if (n > 0 && (!a || !b || !is_device_ptr(a) || !is_device_ptr(b)))
+        return fail(RK_EINVAL, "arrays must be device memory");
+    return ensure_workspace(m, std::max<int64_t>(n, 1));
+}
+
+int rk_dbg_rhs(rk_mech *m, int64_t n, const double *y, double *f, void *stream) {
+    int rc = dbg_common(m, n, y, f);
+    if (rc != RK_OK) return rc;
+    hipError_t e = rk::launch_rhs(m->dev, n, y, f, m->scratch, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? RK_OK : hip_fail(e, "rhs kernel launch");
+}
+
+int rk_dbg_jacobian(rk_mech *m, int64_t n, const double *y, double *J, void *stream) {
+    int rc = dbg_common(m, n, y, J);
+    if (rc != RK_OK) return rc;
+    hipError_t e = rk::launch_jac(m->dev, n, y, J, m->scratch, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? RK_OK : hip_fail(e, "jacobian kernel launch");
+}
+
+}  // extern "C"

@@ -1,0 +1,92 @@
+// Internal types of the rkchem library (host and device).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/rkchem.h"
+
+namespace rk {
+
+constexpr double kRu = 8.314462618;     // J/(mol K)
+constexpr double kPatm = 101325.0;      // Pa
+constexpr int kWave = 64;
+
+// Reaction parameter record (doubles per reaction).
+enum RPar { P_A = 0, P_B, P_EAR, P_A0, P_B0, P_EA0R, P_TA, P_T3, P_T1, P_T2, P_DNU, P_NPAR = 12 };
+
+// Device view of a mechanism.  Reaction/species tables are read with
+// wavefront-uniform indices, so the loads are scalar (constant cache).
+struct DevMech {
+    int K, R, N, n3b;
+    const double *W;       // [K]  kg/mol
+    const double *invW;    // [K]
+    const double *Tmid;    // [K]
+    const double *thermo;  // [K][2][7]: low range then high range
+    const int4 *rsp;       // [R]  reactant slots r0, r1, product slots p0, p1 (-1 = empty)
+    const int *rinfo;      // [R]  kind | nr << 4 | np << 8 | (third-body row + 1) << 12
+    const double *rpar;    // [R][P_NPAR]
+    const double *eff;     // [n3b][K] collision efficiencies
+};
+
+// Radau IIA constants and integrator parameters (computed on the host).
+struct RadauParams {
+    double dt, atol, rtol, kappa, h0, hmin;
+    int kmax, nmax;
+    double g, a, b;          // eigenvalues of A^-1: g, a +- i b
+    double T[9], Ti[9];      // T^-1 A^-1 T = [[g,0,0],[0,a,-b],[0,b,a]] (row-major)
+    double c1, c2;           // collocation nodes (c3 = 1)
+    double d[3];             // error-estimate weights
+};
+
+// Per-lane scratch layout (element offsets; element e of a lane lives at
+// base[e * 64], consecutive lanes in consecutive doubles).
+struct LaneLayout {
+    int y, f0, sc, Z, W, F, dW, Zs, ev, vv, tmp, sc2;
+    int J, E1, E2r, E2i, p1, p2;
+    int C, cp, h, s, dcp, wdot, dwdT, sS;
+    int total;
+};
+
+// Per-state counters written by the integrators: [kNumCounters][n].
+enum Counter { C_STATUS = 0, C_NSTEP, C_NACC, C_NREJ, C_NNEWT, C_NNFAIL, C_NFEV, C_NJEV, C_NLU, kNumCounters };
+
+LaneLayout lane_layout(int K);
+
+// Launchers (rk_kernels.hip).
+hipError_t launch_rhs(const DevMech &m, int64_t n, const double *y, double *f, double *scratch, hipStream_t st);
+hipError_t launch_jac(const DevMech &m, int64_t n, const double *y, double *J, double *scratch, hipStream_t st);
+hipError_t launch_radau_lane(const DevMech &m, const RadauParams &p, int64_t n, const double *yin, double *yout,
+                             double *scratch, int32_t *counters, hipStream_t st);
+size_t lane_scratch_doubles(int K, int64_t n);
+
+}  // namespace rk
+
+// Handle (host side).
+struct rk_mech {
+    int K = 0, R = 0, E = 0, n3b = 0;
+    std::string name;
+    // host copies
+    std::vector<double> W, Tmid, thermo, rpar, eff;
+    std::vector<int> rinfo, comp;
+    std::vector<int4> rsp;
+    // device
+    rk::DevMech dev{};
+    void *dev_block = nullptr;
+    int device = 0;
+    // options
+    int variant = 0;           // 0 lane, 1 wave
+    int kmax = 7, nmax = 100000;
+    double kappa = 0.0, h0 = 0.0;
+    // workspace of the last call
+    double *scratch = nullptr;
+    size_t scratch_cap = 0;    // doubles
+    int32_t *counters = nullptr;
+    int64_t counters_cap = 0;  // states
+    int64_t last_n = 0;
+    hipStream_t last_stream = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool have_run = false;
+};

@@ -1,0 +1,186 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle on the
+same seeded inputs.  Bar (atol 1e-10, rtol 1e-6): max relative error <= 1e-5
+on T and on every Y_i whose oracle value exceeds 1e-8; kernel-level source
+terms and Jacobian to rounding."""
+import numpy as np
+import pytest
+
+from paper_1607_03884_amd import configs, gen
+from tests.parity import banner, integration_errors, rhs_magnitudes, EPS
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch, torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def gm13(torch_dev, m13_path):
+    from paper_1607_03884_amd import Mechanism
+    return Mechanism(m13_path)
+
+
+@pytest.fixture(scope="module")
+def gm53(torch_dev, m53_path):
+    from paper_1607_03884_amd import Mechanism
+    return Mechanism(m53_path)
+
+
+def _dev(torch_dev, rows):
+    torch, dev = torch_dev
+    return torch.from_numpy(gen.to_soa(rows)).to(dev)
+
+
+def _mixed_states(K, n, seed):
+    st = gen.uniform_states(K, n, seed, T_range=(600.0, 3000.0))
+    st[0, 1:K + 1] = 1e-12
+    st[0, 2] = 1.0
+    return st
+
+
+@pytest.mark.parametrize("name", ["M13", "M53"])
+def test_rhs_parity(torch_dev, request, name):
+    banner(f"rhs parity {name}")
+    g = request.getfixturevalue("gm13" if name == "M13" else "gm53")
+    om = request.getfixturevalue("m13" if name == "M13" else "m53")
+    mech = gen.make_mechanism(configs.MECHS[name])
+    st = _mixed_states(mech.K, 300, 3)
+    f = g.dbg_rhs(_dev(torch_dev, st)).cpu().numpy().T
+    for row, fg in zip(st, f):
+        fr = om.rhs(row[:mech.K + 1], row[-1])
+        mag = rhs_magnitudes(mech, om, row)
+        # exp() arguments reach ~50 (Arrhenius, equilibrium constants), so rounding
+        # of the arguments gives ~1e-13 relative errors in the rates
+        assert np.all(np.abs(fg - fr) <= 2000 * EPS * mag + 1e-300), np.max(np.abs(fg - fr) / (mag + 1e-300))
+
+
+@pytest.mark.parametrize("name", ["M13", "M53"])
+def test_jacobian_parity(torch_dev, request, name):
+    banner(f"jacobian parity {name}")
+    g = request.getfixturevalue("gm13" if name == "M13" else "gm53")
+    om = request.getfixturevalue("m13" if name == "M13" else "m53")
+    K = g.K
+    N = K + 1
+    st = _mixed_states(K, 96 if K > 20 else 300, 4)
+    J = g.dbg_jacobian(_dev(torch_dev, st)).cpu().numpy().T.reshape(len(st), N, N)
+    worst = 0.0
+    for row, Jg in zip(st, J):
+        Jr = om.jac(row[:N], row[-1])
+        scale = np.abs(Jr).max(axis=1, keepdims=True) + 1e-300
+        worst = max(worst, float((np.abs(Jg - Jr) / scale).max()))
+    assert worst <= 1e-11, worst
+
+
+def _run(torch_dev, g, rows, dt, **opts):
+    torch, _ = torch_dev
+    for k, v in opts.items():
+        g.set_option(k, v)
+    y = _dev(torch_dev, rows)
+    out = g.integrate(y, dt, 1e-10, 1e-6)
+    torch.cuda.synchronize()
+    st = g.stats(per_state=True)
+    return out.cpu().numpy().T, st
+
+
+def test_cfg0_full_parity(torch_dev, gm13, m13):
+    banner("radau cfg0 4096 states dt=1e-6")
+    rows = configs.states_for(configs.WORKLOADS["cfg0"])
+    got, st = _run(torch_dev, gm13, rows, 1e-6)
+    ref, res = m13.integrate(rows, 1e-6)
+    assert np.all(st["per_state_status"] == 0) and np.all(res["status"] == 0)
+    eT, eY = integration_errors(got, ref, 13)
+    same = np.mean(st["per_state_steps"] == res["nstep"])
+    print(f"cfg0: max rel err T {eT:.2e} Y {eY:.2e}, identical step counts {same:.4f}, "
+          f"kernel {st['kernel_ms']:.1f} ms")
+    assert eT <= TOL and eY <= TOL
+    assert same >= 0.99
+    assert np.array_equal(got[:, -1], rows[:, -1])
+
+
+@pytest.mark.parametrize("n", [1, 63, 65, 130])
+def test_ragged_sizes(torch_dev, gm13, m13, n):
+    banner(f"radau ragged n={n}")
+    rows = configs.states_for(configs.WORKLOADS["cfg0"])[-n:]
+    got, st = _run(torch_dev, gm13, rows, 1e-6)
+    ref, res = m13.integrate(rows, 1e-6)
+    eT, eY = integration_errors(got, ref, 13)
+    assert eT <= TOL and eY <= TOL
+    assert st["n_states"] == n
+
+
+def test_empty_batch(torch_dev, gm13):
+    banner("radau empty batch")
+    torch, dev = torch_dev
+    y = torch.empty((15, 0), dtype=torch.float64, device=dev)
+    out = gm13.integrate(y, 1e-6)
+    torch.cuda.synchronize()
+    assert out.shape == (15, 0)
+    assert gm13.stats()["n_states"] == 0
+
+
+def test_in_place(torch_dev, gm13):
+    banner("radau in place")
+    torch, _ = torch_dev
+    rows = configs.states_for(configs.WORKLOADS["cfg0"], 200)
+    a = gm13.integrate(_dev(torch_dev, rows), 1e-6)
+    y = _dev(torch_dev, rows)
+    b = gm13.integrate(y, 1e-6, y_out=y)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_failure_statuses(torch_dev, gm13):
+    banner("radau failure statuses")
+    rows = configs.states_for(configs.WORKLOADS["cfg0"], 5).copy()
+    rows[0, 4] = np.nan
+    rows[1, 0] = -10.0
+    rows[2, -1] = 0.0
+    got, st = _run(torch_dev, gm13, rows, 1e-6)
+    assert list(st["per_state_status"][:3]) == [3, 3, 3]
+    assert np.array_equal(got[:3], rows[:3], equal_nan=True)
+    assert list(st["per_state_status"][3:]) == [0, 0]
+    got, st = _run(torch_dev, gm13, rows[3:], 1e-6, nmax=1)
+    assert list(st["per_state_status"]) == [1, 1]
+    gm13.set_option("nmax", 100000)
+
+
+def test_options_match_oracle(torch_dev, gm13, m13):
+    banner("radau options kmax=4 kappa=0.01 h0=1e-9")
+    import oracle
+    rows = configs.states_for(configs.WORKLOADS["cfg0"], 256)
+    got, st = _run(torch_dev, gm13, rows, 1e-6, kmax=4, kappa=0.01, h0=1e-9)
+    ref, res = m13.integrate(rows, 1e-6, opts=oracle.default_opts(kmax=4, kappa=0.01, h0=1e-9))
+    for k, v in (("kmax", 7), ("kappa", 0), ("h0", 0)):
+        gm13.set_option(k, v)
+    eT, eY = integration_errors(got, ref, 13)
+    assert eT <= TOL and eY <= TOL
+    assert np.mean(st["per_state_steps"] == res["nstep"]) >= 0.98
+
+
+@pytest.mark.parametrize("dt", [1e-6, 1e-4])
+def test_cfg1_full_size_sampled(torch_dev, gm13, m13, dt):
+    """262,144 PaSR-like states in the benchmark's launch configuration:
+    properties on every state, oracle parity on a sample that includes the
+    states with the most steps."""
+    banner(f"radau cfg1 262144 states dt={dt}")
+    rows = configs.states_for(configs.WORKLOADS["cfg1"])
+    got, st = _run(torch_dev, gm13, rows, dt)
+    status = st["per_state_status"]
+    assert np.all(status == 0)
+    assert np.all(np.isfinite(got))
+    assert np.abs(got[:, 1:14].sum(1) - rows[:, 1:14].sum(1)).max() <= 1e-12
+    steps = st["per_state_steps"]
+    rng = np.random.default_rng(77)
+    top = np.argsort(steps)[-256:]
+    pick = np.unique(np.concatenate([top, rng.choice(len(rows), 768, replace=False)]))
+    ref, res = m13.integrate(rows[pick], dt)
+    eT, eY = integration_errors(got[pick], ref, 13)
+    print(f"cfg1 dt={dt}: kernel {st['kernel_ms']:.1f} ms, steps {st['steps']}, max rel err T {eT:.2e} Y {eY:.2e}, "
+          f"D64 mean {st['d_mean64']:.3f}")
+    assert eT <= TOL and eY <= TOL
