@@ -28,7 +28,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cfg1")
-    ap.add_argument("--variant", default="lane")
+    ap.add_argument("--variant", default="wave")
     ap.add_argument("--cpu-sample", type=int, default=16384)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -103,7 +103,7 @@ def main() -> int:
     achieved = tot_flops / (tot_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
-                "kernel": f"radau_{args.variant}_kernel", "flops_per_launch": tot_flops / len(wl.dts)}
+                "kernel": {"lane": "radau_lane_kernel", "wave": "radau_group_kernel"}.get(args.variant, args.variant), "flops_per_launch": tot_flops / len(wl.dts)}
 
     cpu = None
     parity = None

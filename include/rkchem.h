@@ -103,8 +103,10 @@ int radau_integrate(rk_mech *mech, int64_t n_states, double dt, const double *d_
 int stats_get(rk_mech *mech, rk_stats *out, int32_t *per_state_steps, int32_t *per_state_status);
 
 /* radau_set_option — integrator options of a handle (strings):
- *   "variant"  "lane" (default; one lane per state, the paper's per-thread
- *              pattern) | "wave" (one wavefront cooperates on a state)
+ *   "variant"  "auto" (default: "wave" when K + 1 <= 16, else "lane") |
+ *              "lane" (one lane per state, the paper's per-thread pattern) |
+ *              "wave" (16 lanes of a wavefront cooperate on one state, the
+ *              paper's per-block pattern; persistent work queue; K + 1 <= 16)
  *   "kmax"     max Newton iterations per step (default 7)
  *   "kappa"    Newton stopping constant (default max(10u/rtol, min(0.03, rtol^0.5)))
  *   "nmax"     step-attempt limit per state (default 100000)

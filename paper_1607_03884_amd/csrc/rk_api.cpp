@@ -212,6 +212,20 @@ int upload(rk_mech *m, const std::vector<Rx> &rx, const std::vector<double> &alo
         p[rk::P_DNU] = (double)(x.np - x.nr);
     }
     if (m->eff.empty()) m->eff.push_back(0.0);
+    // species -> (reaction, net nu) lists
+    m->sp_off.assign(K + 1, 0);
+    m->sp_rx.clear();
+    for (int k = 0; k < K; ++k) {
+        m->sp_off[k] = (int)m->sp_rx.size();
+        for (int j = 0; j < R; ++j) {
+            int nu = 0;
+            for (int s = 0; s < rx[j].nr; ++s) nu -= rx[j].r[s] == k;
+            for (int s = 0; s < rx[j].np; ++s) nu += rx[j].p[s] == k;
+            if (nu != 0) m->sp_rx.push_back(int2{j, nu});
+        }
+    }
+    m->sp_off[K] = (int)m->sp_rx.size();
+    if (m->sp_rx.empty()) m->sp_rx.push_back(int2{0, 0});
     std::vector<double> invW(K);
     for (int k = 0; k < K; ++k) invW[k] = 1.0 / m->W[k];
 
@@ -222,7 +236,8 @@ int upload(rk_mech *m, const std::vector<Rx> &rx, const std::vector<double> &alo
         {m->Tmid.data(), K * sizeof(double), 0}, {m->thermo.data(), m->thermo.size() * sizeof(double), 0},
         {m->rsp.data(), std::max(R, 1) * sizeof(int4), 0}, {m->rinfo.data(), std::max(R, 1) * sizeof(int), 0},
         {m->rpar.data(), std::max<size_t>(m->rpar.size(), 1) * sizeof(double), 0},
-        {m->eff.data(), m->eff.size() * sizeof(double), 0}};
+        {m->eff.data(), m->eff.size() * sizeof(double), 0},
+        {m->sp_off.data(), m->sp_off.size() * sizeof(int), 0}, {m->sp_rx.data(), m->sp_rx.size() * sizeof(int2), 0}};
     size_t total = 0;
     for (Part &p : parts) { p.off = total; total += (p.bytes + 255) / 256 * 256; }
     std::vector<char> host(total, 0);
@@ -244,6 +259,8 @@ int upload(rk_mech *m, const std::vector<Rx> &rx, const std::vector<double> &alo
     d.rinfo = reinterpret_cast<const int *>(b + parts[5].off);
     d.rpar = reinterpret_cast<const double *>(b + parts[6].off);
     d.eff = reinterpret_cast<const double *>(b + parts[7].off);
+    d.sp_off = reinterpret_cast<const int *>(b + parts[8].off);
+    d.sp_rx = reinterpret_cast<const int2 *>(b + parts[9].off);
     e = hipEventCreate(&m->ev0);
     if (e == hipSuccess) e = hipEventCreate(&m->ev1);
     if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
@@ -340,6 +357,10 @@ int ensure_workspace(rk_mech *m, int64_t n) {
         }
         m->scratch_cap = need;
     }
+    if (!m->queue && hipMalloc(&m->queue, 256) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(RK_ENOMEM, "cannot allocate the work queue");
+    }
     if (n > m->counters_cap) {
         if (m->counters) { (void)hipDeviceSynchronize(); (void)hipFree(m->counters); m->counters = nullptr; m->counters_cap = 0; }
         if (hipMalloc(&m->counters, (size_t)n * rk::kNumCounters * sizeof(int32_t)) != hipSuccess) {
@@ -385,6 +406,7 @@ void mech_free(rk_mech *m) {
     if (m->dev_block) (void)hipFree(m->dev_block);
     if (m->scratch) (void)hipFree(m->scratch);
     if (m->counters) (void)hipFree(m->counters);
+    if (m->queue) (void)hipFree(m->queue);
     if (m->ev0) (void)hipEventDestroy(m->ev0);
     if (m->ev1) (void)hipEventDestroy(m->ev1);
     delete m;
@@ -404,6 +426,7 @@ int radau_set_option(rk_mech *m, const char *key, const char *value) {
     if (k == "variant") {
         if (v == "lane") m->variant = 0;
         else if (v == "wave") m->variant = 1;
+        else if (v == "auto") m->variant = -1;
         else return fail(RK_EINVAL, "unknown variant " + v);
         return RK_OK;
     }
@@ -430,7 +453,10 @@ int radau_integrate(rk_mech *m, int64_t n, double dt, const double *yin, double 
     if (n > 0 && (!yin || !yout)) return fail(RK_EINVAL, "radau_integrate: NULL state pointer");
     if (n > 0 && (!is_device_ptr(yin) || !is_device_ptr(yout)))
         return fail(RK_EINVAL, "radau_integrate: state arrays must be device memory");
-    if (m->variant != 0) return fail(RK_EINVAL, "radau_integrate: variant not available in this build");
+    const bool group_ok = m->K + 1 <= 16 && rk::group_lds_bytes(m->R) <= 65536;
+    const int variant = m->variant >= 0 ? m->variant : (group_ok ? 1 : 0);
+    if (variant == 1 && !group_ok)
+        return fail(RK_EINVAL, "radau_integrate: the wave variant needs K + 1 <= 16 and fewer than 2000 reactions");
     int rc = ensure_workspace(m, std::max<int64_t>(n, 1));
     if (rc != RK_OK) return rc;
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -446,7 +472,14 @@ int radau_integrate(rk_mech *m, int64_t n, double dt, const double *yin, double 
     p.hmin = 1e-14 * dt;
     hipError_t e = hipEventRecord(m->ev0, st);
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
-    e = rk::launch_radau_lane(m->dev, p, n, yin, yout, m->scratch, m->counters, st);
+    if (variant == 1) {
+        if (m->group_blocks == 0) m->group_blocks = rk::group_max_blocks(m->R);
+        const int64_t need = (n + 3) / 4;
+        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(need, m->group_blocks));
+        e = rk::launch_radau_group(m->dev, p, n, yin, yout, m->counters, m->queue, nullptr, grid, st);
+    } else {
+        e = rk::launch_radau_lane(m->dev, p, n, yin, yout, m->scratch, m->counters, st);
+    }
     if (e != hipSuccess) return hip_fail(e, "radau kernel launch");
     e = hipEventRecord(m->ev1, st);
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord");

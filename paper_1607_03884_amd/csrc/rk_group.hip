@@ -1,0 +1,687 @@
+// Radau IIA with a group of 16 lanes cooperating on one state (the paper's
+// per-block pattern, Sec. 1.2, sized to a quarter wavefront), for mechanisms
+// with N = K + 1 <= 16 unknowns.
+//
+// Lane r of a group owns component r of every vector (r = 0 temperature,
+// r = 1..K mass fractions) and row r of the iteration matrices.  The LU
+// factors of E1 (real) and E2 (complex) stay in registers: partial pivoting
+// is done by row ownership (the pivot row is chosen among the rows not yet
+// used, its lane records the elimination position, nothing moves), so every
+// register index is a compile-time constant.  Per-species and per-reaction
+// intermediates of the source terms and of the Jacobian go through the
+// group's slice of LDS; J itself is assembled and kept in LDS.
+//
+// Work distribution: a persistent grid whose groups pull states from a device
+// queue (one atomic per state), so a group that finishes a cheap state starts
+// the next one at once instead of idling until the costliest state of its
+// wavefront is done.  The states may be visited in a caller-supplied order.
+#include <hip/hip_runtime.h>
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+
+#include "rk_internal.h"
+
+namespace rk {
+
+namespace {
+
+constexpr int G = 16;                          // lanes per state = max N
+constexpr double kU = 2.220446049250313e-16;
+
+__device__ __forceinline__ void sync_wave() { __syncthreads(); }   // blocks are one wavefront
+
+__device__ __forceinline__ double gsum(double v) {
+    v += __shfl_xor(v, 8, G);
+    v += __shfl_xor(v, 4, G);
+    v += __shfl_xor(v, 2, G);
+    v += __shfl_xor(v, 1, G);
+    return v;
+}
+
+__device__ __forceinline__ double gb(double v, int src) { return __shfl(v, src, G); }
+__device__ __forceinline__ int gbi(int v, int src) { return __shfl(v, src, G); }
+
+// lane holding the largest value (ties: lowest lane)
+__device__ __forceinline__ int gargmax(double v, int lane) {
+#pragma unroll
+    for (int off = 8; off >= 1; off >>= 1) {
+        const double ov = __shfl_xor(v, off, G);
+        const int ol = __shfl_xor(lane, off, G);
+        if (ov > v || (ov == v && ol < lane)) { v = ov; lane = ol; }
+    }
+    return lane;
+}
+
+// LDS slice of one group (doubles)
+struct GL {
+    double *C, *h, *s, *rec, *J, *prow;
+};
+
+__host__ __device__ constexpr int group_lds_doubles(int R) { return 3 * G + 8 * R + G * G + 2 * G; }
+
+__device__ __forceinline__ GL group_lds(double *base, int R) {
+    GL L;
+    L.C = base;
+    L.h = base + G;
+    L.s = base + 2 * G;
+    L.rec = base + 3 * G;
+    L.J = L.rec + 8 * R;
+    L.prow = L.J + G * G;
+    return L;
+}
+
+struct Thermo {
+    double cp, h, s, dcp;
+};
+
+__device__ __forceinline__ Thermo species_thermo(const DevMech &m, int k, double T, double lnT, double invT) {
+    const double *lo = m.thermo + (size_t)k * 32;
+    const double *a = T < m.Tmid[k] ? lo : lo + 16;
+    Thermo t;
+    t.cp = a[0] + T * (a[1] + T * (a[2] + T * (a[3] + T * a[4])));
+    t.h = a[5] + T * (a[6] + T * (a[7] + T * (a[8] + T * a[9]))) + a[10] * invT;
+    t.s = a[0] * lnT + T * (a[11] + T * (a[12] + T * (a[13] + T * a[14]))) + a[15];
+    t.dcp = a[1] + T * (2.0 * a[2] + T * (3.0 * a[3] + T * 4.0 * a[4]));
+    return t;
+}
+
+// Per-reaction quantities at (T, C): forward constant (incl. falloff) and its
+// log-derivatives, equilibrium constant.
+struct RxEval {
+    double kf, kr, dlnkf, dlnkf_dM, dlnKc, Mc, Pf, Pp;
+    int kind, nr, np;
+    int4 sp;
+};
+
+__device__ __forceinline__ RxEval eval_reaction(const DevMech &m, const GL &L, int j, double T, double lnT, double invT,
+                                                double lnPRT, bool derivs) {
+    RxEval e;
+    e.sp = m.rsp[j];
+    const int info = m.rinfo[j];
+    const double *p = m.rpar + (size_t)j * P_NPAR;
+    e.kind = info & 15;
+    e.nr = (info >> 4) & 15;
+    e.np = (info >> 8) & 15;
+    const int K = m.K;
+    double kf = p[P_A] * exp(p[P_B] * lnT - p[P_EAR] * invT);
+    double dlnkf = (p[P_B] + p[P_EAR] * invT) * invT;
+    double Mc = 0.0, dlnkf_dM = 0.0;
+    if (e.kind != 0) {
+        const double *ef = m.eff + (size_t)((info >> 12) - 1) * K;
+        for (int k = 0; k < K; ++k) Mc += ef[k] * L.C[k];
+    }
+    if (e.kind == 2) {
+        const double k0 = p[P_A0] * exp(p[P_B0] * lnT - p[P_EA0R] * invT);
+        const double Pr = k0 * Mc / kf;
+        const double ta = p[P_TA], t3 = p[P_T3], t1 = p[P_T1], t2 = p[P_T2];
+        const double e3 = exp(-T / t3), e1 = exp(-T / t1), e2 = exp(-t2 * invT);
+        const double Fc = (1.0 - ta) * e3 + ta * e1 + e2;
+        const double lF = log10(Fc);
+        const double c = -0.4 - 0.67 * lF, nn = 0.75 - 1.27 * lF;
+        const double xx = log10(Pr) + c;
+        const double den = nn - 0.14 * xx;
+        const double f1 = xx / den, g1 = 1.0 + f1 * f1;
+        if (derivs) {
+            const double dlnk0 = (p[P_B0] + p[P_EA0R] * invT) * invT;
+            const double dlnPr = dlnk0 - dlnkf;
+            const double dFc = -(1.0 - ta) / t3 * e3 - ta / t1 * e1 + t2 * invT * invT * e2;
+            const double dlF = dFc / (Fc * M_LN10);
+            const double dxT = dlnPr / M_LN10 - 0.67 * dlF, dnT = -1.27 * dlF;
+            const double df1T = (nn * dxT - xx * dnT) / (den * den);
+            const double dl10F_T = dlF / g1 - 2.0 * lF * f1 * df1T / (g1 * g1);
+            const double df1M = nn / (Mc * M_LN10) / (den * den);
+            const double dl10F_M = -2.0 * lF * f1 * df1M / (g1 * g1);
+            dlnkf = dlnkf + dlnPr / (1.0 + Pr) + M_LN10 * dl10F_T;
+            dlnkf_dM = 1.0 / (Mc * (1.0 + Pr)) + M_LN10 * dl10F_M;
+        }
+        kf = kf * (Pr / (1.0 + Pr)) * exp10(lF / g1);
+    }
+    const int4 sp = e.sp;
+    double dS = L.s[sp.z] - L.s[sp.x];
+    double dH = L.h[sp.z] - L.h[sp.x];
+    double Pf = L.C[sp.x], Pp = L.C[sp.z];
+    if (sp.y >= 0) { dS -= L.s[sp.y]; dH -= L.h[sp.y]; Pf *= L.C[sp.y]; }
+    if (sp.w >= 0) { dS += L.s[sp.w]; dH += L.h[sp.w]; Pp *= L.C[sp.w]; }
+    const double dnu = p[P_DNU];
+    const double Kc = exp(dS - dH + dnu * lnPRT);
+    e.kf = kf;
+    e.kr = kf / Kc;
+    e.dlnkf = dlnkf;
+    e.dlnkf_dM = dlnkf_dM;
+    e.dlnKc = (dH - dnu) * invT;
+    e.Mc = Mc;
+    e.Pf = Pf;
+    e.Pp = Pp;
+    return e;
+}
+
+struct Mix {
+    double T, Wbar, rho, invW, Y, lnT, invT, lnPRT;
+    bool isY;
+    int k;
+};
+
+// mixture quantities and concentrations/thermo into LDS; returns lane data
+__device__ __forceinline__ Mix mixture(const DevMech &m, const GL &L, int r, double yv, double P, Thermo &th) {
+    Mix x;
+    x.T = gb(yv, 0);
+    x.k = r - 1;
+    x.isY = r >= 1 && r <= m.K;
+    x.Y = x.isY ? yv : 0.0;
+    x.invW = x.isY ? m.invW[x.k] : 0.0;
+    const double sumYW = gsum(x.Y * x.invW);
+    x.Wbar = 1.0 / sumYW;
+    x.rho = P * x.Wbar / (kRu * x.T);
+    x.lnT = log(x.T);
+    x.invT = 1.0 / x.T;
+    x.lnPRT = log(kPatm / (kRu * x.T));
+    sync_wave();
+    if (x.isY) {
+        th = species_thermo(m, x.k, x.T, x.lnT, x.invT);
+        L.C[x.k] = x.rho * x.Y * x.invW;
+        L.h[x.k] = th.h;
+        L.s[x.k] = th.s;
+    } else {
+        th = Thermo{0.0, 0.0, 0.0, 0.0};
+    }
+    sync_wave();
+    return x;
+}
+
+// f(y): lane r in, lane r out
+__device__ double rhs_g(const DevMech &m, const GL &L, int r, double yv, double P) {
+    Thermo th;
+    const Mix x = mixture(m, L, r, yv, P, th);
+    for (int j = r; j < m.R; j += G) {
+        const RxEval e = eval_reaction(m, L, j, x.T, x.lnT, x.invT, x.lnPRT, false);
+        double q = e.kf * e.Pf - e.kr * e.Pp;
+        if (e.kind == 1) q *= e.Mc;
+        L.rec[8 * j] = q;
+    }
+    sync_wave();
+    double wdot = 0.0;
+    if (x.isY)
+        for (int i = m.sp_off[x.k]; i < m.sp_off[x.k + 1]; ++i) {
+            const int2 e = m.sp_rx[i];
+            wdot += e.y * L.rec[8 * e.x];
+        }
+    const double hw = gsum(x.isY ? th.h * wdot : 0.0);
+    const double cpm = gsum(x.isY ? x.Y * th.cp * x.invW : 0.0);
+    if (r == 0) return -hw * x.T / (x.rho * cpm);
+    return x.isY ? m.W[x.k] * wdot / x.rho : 0.0;
+}
+
+// Jacobian into L.J (row-major 16 x 16, rows/cols beyond N untouched = 0)
+__device__ void jac_g(const DevMech &m, const GL &L, int r, double yv, double P) {
+    const int K = m.K;
+    Thermo th;
+    const Mix x = mixture(m, L, r, yv, P, th);
+    const double T = x.T, invT = x.invT, rho = x.rho, Wbar = x.Wbar;
+    for (int i = r; i < G * G; i += G) L.J[i] = 0.0;
+    // per-reaction records: q, dq/dT|C, S, dense coefficient, 4 mass-action partials
+    for (int j = r; j < m.R; j += G) {
+        const RxEval e = eval_reaction(m, L, j, T, x.lnT, invT, x.lnPRT, true);
+        const double Rj = e.kf * e.Pf - e.kr * e.Pp;
+        const double dRdT = Rj * e.dlnkf + e.kr * e.Pp * e.dlnKc;
+        const double sMA = e.kind == 1 ? e.Mc : 1.0;
+        const double ctb = e.kind == 1 ? Rj : (e.kind == 2 ? Rj * e.dlnkf_dM : 0.0);
+        const int4 sp = e.sp;
+        const double Cr0 = L.C[sp.x], Cr1 = sp.y >= 0 ? L.C[sp.y] : 1.0;
+        const double Cp0 = L.C[sp.z], Cp1 = sp.w >= 0 ? L.C[sp.w] : 1.0;
+        double *rc = L.rec + 8 * j;
+        rc[0] = sMA * Rj;
+        rc[1] = sMA * dRdT;
+        rc[2] = sMA * (e.nr * e.kf * e.Pf - e.np * e.kr * e.Pp) + ctb * e.Mc;
+        rc[3] = ctb;
+        rc[4] = sMA * e.kf * Cr1;
+        rc[5] = sMA * e.kf * Cr0;
+        rc[6] = -sMA * e.kr * Cp1;
+        rc[7] = -sMA * e.kr * Cp0;
+    }
+    sync_wave();
+    // Mkm = sum_j nu_kj dq_j/dC_m into the Y block; lane r owns column r (species r-1)
+    if (x.isY) {
+        const int mm = x.k;
+        for (int j = 0; j < m.R; ++j) {
+            const int4 sp = m.rsp[j];
+            const int info = m.rinfo[j];
+            const double *rc = L.rec + 8 * j;
+            double dq = 0.0;
+            if (mm == sp.x) dq += rc[4];
+            if (mm == sp.y) dq += rc[5];
+            if (mm == sp.z) dq += rc[6];
+            if (mm == sp.w) dq += rc[7];
+            if (info & 15) dq += rc[3] * m.eff[(size_t)((info >> 12) - 1) * K + mm];
+            if (dq != 0.0) {
+                L.J[(1 + sp.x) * G + r] -= dq;
+                if (sp.y >= 0) L.J[(1 + sp.y) * G + r] -= dq;
+                L.J[(1 + sp.z) * G + r] += dq;
+                if (sp.w >= 0) L.J[(1 + sp.w) * G + r] += dq;
+            }
+        }
+    }
+    // species sums
+    double wdot = 0.0, dwdT = 0.0, sS = 0.0;
+    if (x.isY)
+        for (int i = m.sp_off[x.k]; i < m.sp_off[x.k + 1]; ++i) {
+            const int2 e = m.sp_rx[i];
+            const double *rc = L.rec + 8 * e.x;
+            wdot += e.y * rc[0];
+            dwdT += e.y * rc[1];
+            sS += e.y * rc[2];
+        }
+    sync_wave();
+    // temperature row (lane r: column r)
+    const double hk = th.h * T;
+    const double cpmix = gsum(x.Y * th.cp * x.invW);
+    const double dcpmix = gsum(x.Y * th.dcp * x.invW);
+    const double hw = gsum(x.isY ? hk * wdot : 0.0);
+    const double dHdT = gsum(x.isY ? th.cp * wdot + hk * (dwdT - sS * invT) : 0.0);
+    const double hsS = gsum(x.isY ? hk * sS : 0.0);
+    const double rcp = rho * cpmix;
+    const double fT = -hw / rcp;
+    if (x.isY) {
+        double hM = 0.0;
+        for (int k = 0; k < K; ++k) hM += L.h[k] * T * L.J[(1 + k) * G + r];
+        const double dHdY = (rho * hM - Wbar * hsS) * x.invW;
+        L.J[r] = -dHdY / rcp - fT * (th.cp * x.invW / cpmix - Wbar * x.invW);
+    }
+    if (r == 0) L.J[0] = -dHdT / rcp - fT * (-invT + dcpmix / cpmix);
+    sync_wave();
+    // species rows (lane r: row r)
+    if (x.isY) {
+        const double Wk = m.W[x.k];
+        const double fk = Wk * wdot / rho;
+        const double a = Wbar * (fk - Wk * sS / rho);
+        double *row = L.J + r * G;
+        row[0] = Wk / rho * (dwdT - sS * invT) + fk * invT;
+        for (int c = 1; c <= K; ++c) row[c] = (Wk * row[c] + a) * m.invW[c - 1];
+    }
+    sync_wave();
+}
+
+// ---------------------------------------------------------------------------
+// LU by row ownership.  Lane r holds row r; pos = elimination step at which the
+// row became pivot (-1 while unused), perm packs the pivot lane of each step in
+// 4-bit fields.  After factorisation a row holds its multipliers at the columns
+// of the steps it was eliminated in and its U entries from its pivot column on.
+// ---------------------------------------------------------------------------
+struct LUR {
+    double a[G];
+    double dinv;
+    int pos;
+    uint64_t perm;
+};
+
+struct LUC {
+    double re[G], im[G];
+    double dr, di;    // 1 / pivot
+    int pos;
+    uint64_t perm;
+};
+
+__device__ void factor_real(LUR &F, const GL &L, int r, int N) {
+    bool used = r >= N;
+    F.pos = -1;
+    F.perm = 0;
+    F.dinv = 0.0;
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+        if (k < N) {
+            const double v = used ? -1.0 : fabs(F.a[k]);
+            const int p = gargmax(v, r);
+            F.perm |= (uint64_t)p << (4 * k);
+            if (r == p) {
+                used = true;
+                F.pos = k;
+                F.dinv = 1.0 / F.a[k];
+#pragma unroll
+                for (int c = 0; c < G; ++c) L.prow[c] = F.a[c];
+            }
+            sync_wave();
+            if (!used) {
+                const double l = F.a[k] * (1.0 / L.prow[k]);
+                F.a[k] = l;
+#pragma unroll
+                for (int c = k + 1; c < G; ++c) F.a[c] -= l * L.prow[c];
+            }
+            sync_wave();
+        }
+    }
+}
+
+__device__ void factor_cplx(LUC &F, const GL &L, int r, int N) {
+    bool used = r >= N;
+    F.pos = -1;
+    F.perm = 0;
+    F.dr = F.di = 0.0;
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+        if (k < N) {
+            const double v = used ? -1.0 : F.re[k] * F.re[k] + F.im[k] * F.im[k];
+            const int p = gargmax(v, r);
+            F.perm |= (uint64_t)p << (4 * k);
+            if (r == p) {
+                used = true;
+                F.pos = k;
+                const double dd = 1.0 / (F.re[k] * F.re[k] + F.im[k] * F.im[k]);
+                F.dr = F.re[k] * dd;
+                F.di = -F.im[k] * dd;
+#pragma unroll
+                for (int c = 0; c < G; ++c) { L.prow[c] = F.re[c]; L.prow[G + c] = F.im[c]; }
+            }
+            sync_wave();
+            if (!used) {
+                const double pr = L.prow[k], pi = L.prow[G + k];
+                const double dd = 1.0 / (pr * pr + pi * pi);
+                const double ir = pr * dd, ii = -pi * dd;
+                const double xr = F.re[k], xi = F.im[k];
+                const double lr = xr * ir - xi * ii, li = xr * ii + xi * ir;
+                F.re[k] = lr;
+                F.im[k] = li;
+#pragma unroll
+                for (int c = k + 1; c < G; ++c) {
+                    const double ur = L.prow[c], ui = L.prow[G + c];
+                    F.re[c] -= lr * ur - li * ui;
+                    F.im[c] -= lr * ui + li * ur;
+                }
+            }
+            sync_wave();
+        }
+    }
+}
+
+// solve with the factors: b (component r in lane r) -> x (component r in lane r)
+__device__ double solve_real(const LUR &F, int r, int N, double b) {
+    double acc = b;
+#pragma unroll
+    for (int k = 0; k < G; ++k)
+        if (k < N) {
+            const double yk = gb(acc, (int)((F.perm >> (4 * k)) & 15));
+            if (F.pos > k) acc -= F.a[k] * yk;
+        }
+#pragma unroll
+    for (int k = G - 1; k >= 0; --k)
+        if (k < N) {
+            if (F.pos == k) acc *= F.dinv;
+            const double xk = gb(acc, (int)((F.perm >> (4 * k)) & 15));
+            if (F.pos >= 0 && F.pos < k) acc -= F.a[k] * xk;
+        }
+    const int src = r < N ? (int)((F.perm >> (4 * r)) & 15) : r;
+    const double x = gb(acc, src);
+    return r < N ? x : 0.0;
+}
+
+__device__ void solve_cplx(const LUC &F, int r, int N, double &br, double &bi) {
+    double ar = br, ai = bi;
+#pragma unroll
+    for (int k = 0; k < G; ++k)
+        if (k < N) {
+            const int p = (int)((F.perm >> (4 * k)) & 15);
+            const double yr = gb(ar, p), yi = gb(ai, p);
+            if (F.pos > k) {
+                ar -= F.re[k] * yr - F.im[k] * yi;
+                ai -= F.re[k] * yi + F.im[k] * yr;
+            }
+        }
+#pragma unroll
+    for (int k = G - 1; k >= 0; --k)
+        if (k < N) {
+            if (F.pos == k) {
+                const double tr = ar * F.dr - ai * F.di;
+                ai = ar * F.di + ai * F.dr;
+                ar = tr;
+            }
+            const int p = (int)((F.perm >> (4 * k)) & 15);
+            const double xr = gb(ar, p), xi = gb(ai, p);
+            if (F.pos >= 0 && F.pos < k) {
+                ar -= F.re[k] * xr - F.im[k] * xi;
+                ai -= F.re[k] * xi + F.im[k] * xr;
+            }
+        }
+    const int src = r < N ? (int)((F.perm >> (4 * r)) & 15) : r;
+    const double xr = gb(ar, src), xi = gb(ai, src);
+    br = r < N ? xr : 0.0;
+    bi = r < N ? xi : 0.0;
+}
+
+enum { ACT_JAC = 0, ACT_LU = 1, ACT_SAME = 2 };
+
+__global__ void reset_queue_kernel(int *q) { *q = 0; }
+
+__global__ __launch_bounds__(64) void radau_group_kernel(DevMech m, RadauParams rp, int64_t n,
+                                                         const double *__restrict__ yin, double *__restrict__ yout,
+                                                         int32_t *__restrict__ cnt, int *__restrict__ queue,
+                                                         const int *__restrict__ order) {
+    extern __shared__ double smem[];
+    const int r = threadIdx.x & (G - 1);
+    const int grp = threadIdx.x / G;
+    const int N = m.N, K = m.K;
+    const GL L = group_lds(smem + (size_t)grp * group_lds_doubles(m.R), m.R);
+    const bool comp = r < N;                       // lane holds a state component
+    const double dt = rp.dt, atol = rp.atol, rtol = rp.rtol, kappa = rp.kappa;
+    const int kmax = rp.kmax;
+
+    LUR E1;
+    LUC E2;
+    for (;;) {
+        int qi = 0;
+        if (r == 0) qi = atomicAdd(queue, 1);
+        qi = gbi(qi, 0);
+        if (qi >= n) break;
+        const int64_t s = order ? (int64_t)order[qi] : (int64_t)qi;
+
+        const double P = yin[(size_t)(K + 1) * n + s];
+        double y = comp ? yin[(size_t)r * n + s] : 0.0;
+        const double bad_l = (comp && !isfinite(y)) || (r == 0 && !(y > 0.0)) || (r == 0 && !(P > 0.0 && isfinite(P)));
+        const bool bad = gsum(bad_l ? 1.0 : 0.0) > 0.0;
+        int status = RK_ST_OK, nstep = 0, nacc = 0, nrej = 0, nnewt = 0, nnf = 0, nfev = 0, njev = 0, nlu = 0;
+        if (bad) {
+            status = RK_ST_NONFINITE;
+            if (comp) yout[(size_t)r * n + s] = y;
+            if (r == 0) yout[(size_t)(K + 1) * n + s] = P;
+        } else {
+            double t = 0.0, h = rp.h0;
+            bool last = false;
+            if (t + 1.0001 * h >= dt) { h = dt - t; last = true; }
+            double f0 = rhs_g(m, L, r, y, P);
+            ++nfev;
+            double sc = comp ? atol + rtol * fabs(y) : 1.0;
+            bool first = true, reject = false, jac_fresh = false;
+            double eta = 1.0, theta = 1.0, hacc = h, erracc = 1e-2, hlast = h;
+            double Zs1 = 0.0, Zs2 = 0.0, Zs3 = 0.0;
+            int action = ACT_JAC;
+            for (;;) {
+                if (action == ACT_JAC) {
+                    jac_g(m, L, r, y, P);
+                    ++njev;
+                    jac_fresh = true;
+                    action = ACT_LU;
+                }
+                if (action == ACT_LU) {
+                    const double gh = rp.g / h, ah = rp.a / h, bh = rp.b / h;
+                    const double *row = L.J + r * G;
+#pragma unroll
+                    for (int c = 0; c < G; ++c) {
+                        const double j = comp ? row[c] : 0.0;
+                        E1.a[c] = -j;
+                        E2.re[c] = -j;
+                        E2.im[c] = 0.0;
+                    }
+#pragma unroll
+                    for (int c = 0; c < G; ++c)
+                        if (c == r) { E1.a[c] += gh; E2.re[c] += ah; E2.im[c] = bh; }
+                    sync_wave();
+                    factor_real(E1, L, r, N);
+                    factor_cplx(E2, L, r, N);
+                    ++nlu;
+                }
+                action = ACT_SAME;
+                if (nstep >= rp.nmax) { status = RK_ST_STEP_LIMIT; break; }
+                if (h < rp.hmin) { status = RK_ST_H_UNDERFLOW; break; }
+                ++nstep;
+
+                // starting values (collocation polynomial of the previous step)
+                double Z1, Z2, Z3;
+                if (first) {
+                    Z1 = Z2 = Z3 = 0.0;
+                } else {
+                    const double c1 = rp.c1, c2 = rp.c2, q = h / hlast;
+                    const double t1 = 1.0 + c1 * q, t2 = 1.0 + c2 * q, t3 = 1.0 + q;
+                    const double d01 = Zs1 / c1, d12 = (Zs2 - Zs1) / (c2 - c1), d23 = (Zs3 - Zs2) / (1.0 - c2);
+                    const double d012 = (d12 - d01) / c2, d123 = (d23 - d12) / (1.0 - c1);
+                    const double d0123 = d123 - d012;
+                    Z1 = t1 * (d01 + (t1 - c1) * (d012 + (t1 - c2) * d0123)) - Zs3;
+                    Z2 = t2 * (d01 + (t2 - c1) * (d012 + (t2 - c2) * d0123)) - Zs3;
+                    Z3 = t3 * (d01 + (t3 - c1) * (d012 + (t3 - c2) * d0123)) - Zs3;
+                }
+                double W1 = rp.Ti[0] * Z1 + rp.Ti[1] * Z2 + rp.Ti[2] * Z3;
+                double W2 = rp.Ti[3] * Z1 + rp.Ti[4] * Z2 + rp.Ti[5] * Z3;
+                double W3 = rp.Ti[6] * Z1 + rp.Ti[7] * Z2 + rp.Ti[8] * Z3;
+
+                eta = pow(fmax(eta, kU), 0.8);
+                bool converged = false;
+                int newt = 0;
+                double dn_old = 1.0;
+                for (int it = 1; it <= kmax; ++it) {
+                    const double F1 = rhs_g(m, L, r, y + Z1, P);
+                    const double F2 = rhs_g(m, L, r, y + Z2, P);
+                    const double F3 = rhs_g(m, L, r, y + Z3, P);
+                    nfev += 3;
+                    const double gh = rp.g / h, ah = rp.a / h, bh = rp.b / h;
+                    const double G1 = rp.Ti[0] * F1 + rp.Ti[1] * F2 + rp.Ti[2] * F3;
+                    const double G2 = rp.Ti[3] * F1 + rp.Ti[4] * F2 + rp.Ti[5] * F3;
+                    const double G3 = rp.Ti[6] * F1 + rp.Ti[7] * F2 + rp.Ti[8] * F3;
+                    double dW1 = comp ? G1 - gh * W1 : 0.0;
+                    double dW2 = comp ? G2 - (ah * W2 - bh * W3) : 0.0;
+                    double dW3 = comp ? G3 - (bh * W2 + ah * W3) : 0.0;
+                    dW1 = solve_real(E1, r, N, dW1);
+                    solve_cplx(E2, r, N, dW2, dW3);
+                    const double dZ1 = rp.T[0] * dW1 + rp.T[1] * dW2 + rp.T[2] * dW3;
+                    const double dZ2 = rp.T[3] * dW1 + rp.T[4] * dW2 + rp.T[5] * dW3;
+                    const double dZ3 = rp.T[6] * dW1 + rp.T[7] * dW2 + rp.T[8] * dW3;
+                    ++nnewt;
+                    newt = it;
+                    const double dn = sqrt(gsum(comp ? (dZ1 * dZ1 + dZ2 * dZ2 + dZ3 * dZ3) / (sc * sc) : 0.0) / (3 * N));
+                    if (!isfinite(dn)) break;
+                    if (it >= 2) {
+                        const double th = dn / dn_old;
+                        theta = th;
+                        if (th >= 0.99) break;
+                        eta = th / (1.0 - th);
+                        if (pow(th, (double)(kmax - it)) / (1.0 - th) * dn > kappa) break;
+                    }
+                    dn_old = fmax(dn, kU);
+                    Z1 += dZ1; Z2 += dZ2; Z3 += dZ3;
+                    W1 += dW1; W2 += dW2; W3 += dW3;
+                    if (eta * dn <= kappa) { converged = true; break; }
+                }
+                if (!converged) {
+                    ++nnf;
+                    h *= 0.5;
+                    reject = true;
+                    last = false;
+                    action = jac_fresh ? ACT_LU : ACT_JAC;
+                    continue;
+                }
+
+                // embedded error estimate
+                const double invh = 1.0 / h;
+                const double dz = (rp.d[0] * Z1 + rp.d[1] * Z2 + rp.d[2] * Z3) * invh;
+                const double sc2 = comp ? atol + rtol * fmax(fabs(y), fabs(y + Z3)) : 1.0;
+                double ev = solve_real(E1, r, N, comp ? f0 + dz : 0.0);
+                double err = fmax(sqrt(gsum(comp ? (ev / sc2) * (ev / sc2) : 0.0) / N), 1e-10);
+                if (err >= 1.0 && (first || reject)) {
+                    const double fe = rhs_g(m, L, r, y + ev, P);
+                    ++nfev;
+                    ev = solve_real(E1, r, N, comp ? fe + dz : 0.0);
+                    err = fmax(sqrt(gsum(comp ? (ev / sc2) * (ev / sc2) : 0.0) / N), 1e-10);
+                }
+                if (!isfinite(err)) err = 1e300;
+
+                const double fac = fmin(0.9, 0.9 * (2 * kmax + 1) / (double)(2 * kmax + newt));
+                double quot = fmax(0.125, fmin(5.0, pow(err, 0.25) / fac));
+                double hnew = h / quot;
+                if (err < 1.0) {
+                    first = false;
+                    ++nacc;
+                    if (nacc > 1) {
+                        double fg = (hacc / h) * pow(err * err / erracc, 0.25) / 0.9;
+                        fg = fmax(0.125, fmin(5.0, fg));
+                        quot = fmax(quot, fg);
+                        hnew = h / quot;
+                    }
+                    hacc = h;
+                    erracc = fmax(1e-2, err);
+                    Zs1 = Z1; Zs2 = Z2; Zs3 = Z3;
+                    hlast = h;
+                    y = comp ? y + Z3 : 0.0;
+                    sc = comp ? atol + rtol * fabs(y) : 1.0;
+                    t = last ? dt : t + h;
+                    jac_fresh = false;
+                    if (last) break;
+                    f0 = rhs_g(m, L, r, y, P);
+                    ++nfev;
+                    if (reject) hnew = fmin(hnew, h);
+                    reject = false;
+                    if (t + hnew >= dt) {
+                        h = dt - t;
+                        last = true;
+                    } else {
+                        const double qt = hnew / h;
+                        if (theta <= 1e-3 && qt >= 1.0 && qt <= 1.2) { action = ACT_SAME; continue; }
+                        h = hnew;
+                    }
+                    action = theta <= 1e-3 ? ACT_LU : ACT_JAC;
+                } else {
+                    ++nrej;
+                    reject = true;
+                    last = false;
+                    h = first ? 0.1 * h : hnew;
+                    action = jac_fresh ? ACT_LU : ACT_JAC;
+                }
+            }
+            if (comp) yout[(size_t)r * n + s] = y;
+            if (r == 0) yout[(size_t)(K + 1) * n + s] = P;
+        }
+        if (r == 0) {
+            cnt[(size_t)C_STATUS * n + s] = status;
+            cnt[(size_t)C_NSTEP * n + s] = nstep;
+            cnt[(size_t)C_NACC * n + s] = nacc;
+            cnt[(size_t)C_NREJ * n + s] = nrej;
+            cnt[(size_t)C_NNEWT * n + s] = nnewt;
+            cnt[(size_t)C_NNFAIL * n + s] = nnf;
+            cnt[(size_t)C_NFEV * n + s] = nfev;
+            cnt[(size_t)C_NJEV * n + s] = njev;
+            cnt[(size_t)C_NLU * n + s] = nlu;
+        }
+    }
+}
+
+}  // namespace
+
+size_t group_lds_bytes(int R) { return (size_t)(kWave / G) * group_lds_doubles(R) * sizeof(double); }
+
+hipError_t launch_radau_group(const DevMech &m, const RadauParams &p, int64_t n, const double *yin, double *yout,
+                              int32_t *counters, int *queue, const int *order, int grid, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    if (m.N > G) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(1), 0, st, queue);
+    hipLaunchKernelGGL(radau_group_kernel, dim3(grid), dim3(kWave), group_lds_bytes(m.R), st, m, p, n, yin, yout,
+                       counters, queue, order);
+    return hipGetLastError();
+}
+
+int group_max_blocks(int R) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, radau_group_kernel, kWave, group_lds_bytes(R)) !=
+        hipSuccess)
+        per_cu = 1;
+    int dev = 0, cus = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    return std::max(1, per_cu) * std::max(1, cus);
+}
+
+}  // namespace rk

@@ -29,6 +29,8 @@ struct DevMech {
     const int *rinfo;      // [R]  kind | nr << 4 | np << 8 | (third-body row + 1) << 12
     const double *rpar;    // [R][P_NPAR]
     const double *eff;     // [n3b][K] collision efficiencies
+    const int *sp_off;     // [K+1] species -> reaction list offsets
+    const int2 *sp_rx;     // [sp_off[K]] (reaction, net stoichiometric coefficient)
 };
 
 // Radau IIA constants and integrator parameters (computed on the host).
@@ -61,6 +63,11 @@ hipError_t launch_jac(const DevMech &m, int64_t n, const double *y, double *J, d
 hipError_t launch_radau_lane(const DevMech &m, const RadauParams &p, int64_t n, const double *yin, double *yout,
                              double *scratch, int32_t *counters, hipStream_t st);
 size_t lane_scratch_doubles(int K, int64_t n);
+// group-cooperative variant (16 lanes per state, N <= 16), persistent work queue
+hipError_t launch_radau_group(const DevMech &m, const RadauParams &p, int64_t n, const double *yin, double *yout,
+                              int32_t *counters, int *queue, const int *order, int grid, hipStream_t st);
+int group_max_blocks(int R);
+size_t group_lds_bytes(int R);
 
 }  // namespace rk
 
@@ -72,12 +79,14 @@ struct rk_mech {
     std::vector<double> W, Tmid, thermo, rpar, eff;
     std::vector<int> rinfo, comp;
     std::vector<int4> rsp;
+    std::vector<int> sp_off;
+    std::vector<int2> sp_rx;
     // device
     rk::DevMech dev{};
     void *dev_block = nullptr;
     int device = 0;
     // options
-    int variant = 0;           // 0 lane, 1 wave
+    int variant = -1;          // -1 auto, 0 lane, 1 wave (16-lane groups)
     int kmax = 7, nmax = 100000;
     double kappa = 0.0, h0 = 0.0;
     // workspace of the last call
@@ -85,6 +94,8 @@ struct rk_mech {
     size_t scratch_cap = 0;    // doubles
     int32_t *counters = nullptr;
     int64_t counters_cap = 0;  // states
+    int *queue = nullptr;      // work-queue head (device)
+    int group_blocks = 0;      // resident blocks of the group kernel (cached)
     int64_t last_n = 0;
     hipStream_t last_stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;

@@ -88,10 +88,14 @@ def _run(torch_dev, g, rows, dt, **opts):
     return out.cpu().numpy().T, st
 
 
-def test_cfg0_full_parity(torch_dev, gm13, m13):
-    banner("radau cfg0 4096 states dt=1e-6")
+VARIANTS = ["lane", "wave"]
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_cfg0_full_parity(torch_dev, gm13, m13, variant):
+    banner(f"radau cfg0 4096 states dt=1e-6 variant={variant}")
     rows = configs.states_for(configs.WORKLOADS["cfg0"])
-    got, st = _run(torch_dev, gm13, rows, 1e-6)
+    got, st = _run(torch_dev, gm13, rows, 1e-6, variant=variant)
     ref, res = m13.integrate(rows, 1e-6)
     assert np.all(st["per_state_status"] == 0) and np.all(res["status"] == 0)
     eT, eY = integration_errors(got, ref, 13)
@@ -101,13 +105,16 @@ def test_cfg0_full_parity(torch_dev, gm13, m13):
     assert eT <= TOL and eY <= TOL
     assert same >= 0.99
     assert np.array_equal(got[:, -1], rows[:, -1])
+    gm13.set_option("variant", "lane")
 
 
-@pytest.mark.parametrize("n", [1, 63, 65, 130])
-def test_ragged_sizes(torch_dev, gm13, m13, n):
-    banner(f"radau ragged n={n}")
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("n", [1, 3, 63, 65, 130])
+def test_ragged_sizes(torch_dev, gm13, m13, n, variant):
+    banner(f"radau ragged n={n} variant={variant}")
     rows = configs.states_for(configs.WORKLOADS["cfg0"])[-n:]
-    got, st = _run(torch_dev, gm13, rows, 1e-6)
+    got, st = _run(torch_dev, gm13, rows, 1e-6, variant=variant)
+    gm13.set_option("variant", "lane")
     ref, res = m13.integrate(rows, 1e-6)
     eT, eY = integration_errors(got, ref, 13)
     assert eT <= TOL and eY <= TOL
@@ -135,19 +142,21 @@ def test_in_place(torch_dev, gm13):
     assert torch.equal(a, b)
 
 
-def test_failure_statuses(torch_dev, gm13):
-    banner("radau failure statuses")
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_failure_statuses(torch_dev, gm13, variant):
+    banner(f"radau failure statuses variant={variant}")
     rows = configs.states_for(configs.WORKLOADS["cfg0"], 5).copy()
     rows[0, 4] = np.nan
     rows[1, 0] = -10.0
     rows[2, -1] = 0.0
-    got, st = _run(torch_dev, gm13, rows, 1e-6)
+    got, st = _run(torch_dev, gm13, rows, 1e-6, variant=variant)
     assert list(st["per_state_status"][:3]) == [3, 3, 3]
     assert np.array_equal(got[:3], rows[:3], equal_nan=True)
     assert list(st["per_state_status"][3:]) == [0, 0]
     got, st = _run(torch_dev, gm13, rows[3:], 1e-6, nmax=1)
     assert list(st["per_state_status"]) == [1, 1]
     gm13.set_option("nmax", 100000)
+    gm13.set_option("variant", "lane")
 
 
 def test_options_match_oracle(torch_dev, gm13, m13):
@@ -163,14 +172,16 @@ def test_options_match_oracle(torch_dev, gm13, m13):
     assert np.mean(st["per_state_steps"] == res["nstep"]) >= 0.98
 
 
+@pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("dt", [1e-6, 1e-4])
-def test_cfg1_full_size_sampled(torch_dev, gm13, m13, dt):
+def test_cfg1_full_size_sampled(torch_dev, gm13, m13, dt, variant):
     """262,144 PaSR-like states in the benchmark's launch configuration:
     properties on every state, oracle parity on a sample that includes the
     states with the most steps."""
-    banner(f"radau cfg1 262144 states dt={dt}")
+    banner(f"radau cfg1 262144 states dt={dt} variant={variant}")
     rows = configs.states_for(configs.WORKLOADS["cfg1"])
-    got, st = _run(torch_dev, gm13, rows, dt)
+    got, st = _run(torch_dev, gm13, rows, dt, variant=variant)
+    gm13.set_option("variant", "lane")
     status = st["per_state_status"]
     assert np.all(status == 0)
     assert np.all(np.isfinite(got))
