@@ -31,34 +31,58 @@ constexpr double kU = 2.220446049250313e-16;
 
 __device__ __forceinline__ void sync_wave() { __syncthreads(); }   // blocks are one wavefront
 
+// In-row (16-lane) data-parallel moves.  Every reduction below gives the same
+// bits in all 16 lanes (pairwise combinations of equal operands), so group
+// control decisions taken on reduced values are uniform within the group.
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)u, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+template <int CTRL>
+__device__ __forceinline__ uint64_t dppu(uint64_t u) {
+    const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)u, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, false);
+    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+constexpr int kRowMirror = 0x140, kRowHalfMirror = 0x141, kQuadXor2 = 0x4E, kQuadXor1 = 0xB1;
+
 __device__ __forceinline__ double gsum(double v) {
-    v += __shfl_xor(v, 8, G);
-    v += __shfl_xor(v, 4, G);
-    v += __shfl_xor(v, 2, G);
-    v += __shfl_xor(v, 1, G);
+    v = v + dpp<kRowMirror>(v);        // lanes i, 15-i
+    v = v + dpp<kRowHalfMirror>(v);    // ... and 7-i, 8+i (within each half)
+    v = v + dpp<kQuadXor2>(v);
+    v = v + dpp<kQuadXor1>(v);
+    return v;
+}
+
+__device__ __forceinline__ uint64_t gmaxu(uint64_t v) {
+    uint64_t o;
+    o = dppu<kRowMirror>(v); v = o > v ? o : v;
+    o = dppu<kRowHalfMirror>(v); v = o > v ? o : v;
+    o = dppu<kQuadXor2>(v); v = o > v ? o : v;
+    o = dppu<kQuadXor1>(v); v = o > v ? o : v;
     return v;
 }
 
 __device__ __forceinline__ double gb(double v, int src) { return __shfl(v, src, G); }
 __device__ __forceinline__ int gbi(int v, int src) { return __shfl(v, src, G); }
 
-// lane holding the largest value (ties: lowest lane)
-__device__ __forceinline__ int gargmax(double v, int lane) {
-#pragma unroll
-    for (int off = 8; off >= 1; off >>= 1) {
-        const double ov = __shfl_xor(v, off, G);
-        const int ol = __shfl_xor(lane, off, G);
-        if (ov > v || (ov == v && ol < lane)) { v = ov; lane = ol; }
-    }
-    return lane;
+// Pivot choice: lane whose non-negative magnitude is largest; key = magnitude
+// bits with the 4 low mantissa bits replaced by (15 - lane), so equal
+// magnitudes go to the lowest lane; rows already used carry key 0.
+__device__ __forceinline__ int gpivot(double mag, bool used, int lane) {
+    const uint64_t key = used ? 0ull : ((__builtin_bit_cast(uint64_t, mag) & ~0xFull) | (uint64_t)(15 - lane));
+    return 15 - (int)(gmaxu(key) & 0xF);
 }
 
 // LDS slice of one group (doubles)
 struct GL {
-    double *C, *h, *s, *rec, *J, *prow;
+    double *C, *h, *s, *rec, *J, *prow, *vx;
 };
 
-__host__ __device__ constexpr int group_lds_doubles(int R) { return 3 * G + 8 * R + G * G + 2 * G; }
+__host__ __device__ constexpr int group_lds_doubles(int R) { return 3 * G + 8 * R + G * G + 2 * G + 4 * G; }
 
 __device__ __forceinline__ GL group_lds(double *base, int R) {
     GL L;
@@ -68,6 +92,7 @@ __device__ __forceinline__ GL group_lds(double *base, int R) {
     L.rec = base + 3 * G;
     L.J = L.rec + 8 * R;
     L.prow = L.J + G * G;
+    L.vx = L.prow + 2 * G;
     return L;
 }
 
@@ -302,46 +327,69 @@ __device__ void jac_g(const DevMech &m, const GL &L, int r, double yv, double P)
 }
 
 // ---------------------------------------------------------------------------
-// LU by row ownership.  Lane r holds row r; pos = elimination step at which the
-// row became pivot (-1 while unused), perm packs the pivot lane of each step in
-// 4-bit fields.  After factorisation a row holds its multipliers at the columns
-// of the steps it was eliminated in and its U entries from its pivot column on.
+// LU with partial pivoting by row ownership, then rows moved to pivot order.
+// Step k picks, among the rows not yet used, the one with the largest
+// magnitude in column k; its lane broadcasts the row through LDS and the
+// remaining rows are eliminated (every register index is a compile-time
+// constant).  Afterwards the rows are permuted so that lane k holds row k of
+// L\U (P E = L U), which lets the substitutions broadcast from lane k with an
+// in-row DPP move.
 // ---------------------------------------------------------------------------
 struct LUR {
     double a[G];
-    double dinv;
-    int pos;
-    uint64_t perm;
+    double dinv;      // 1 / U_kk of the lane's row
+    uint64_t perm;    // pivot lane of step k in bits 4k..4k+3
 };
 
 struct LUC {
     double re[G], im[G];
-    double dr, di;    // 1 / pivot
-    int pos;
+    double dr, di;    // 1 / U_kk
     uint64_t perm;
 };
 
+// value of lane k of the 16-lane row (row_newbcast:k); k is a constant once the
+// calling loops are unrolled, so the switch folds away
+__device__ __forceinline__ double bcast(double v, int k) {
+    switch (k) {
+        case 0: return dpp<0x150>(v);
+        case 1: return dpp<0x151>(v);
+        case 2: return dpp<0x152>(v);
+        case 3: return dpp<0x153>(v);
+        case 4: return dpp<0x154>(v);
+        case 5: return dpp<0x155>(v);
+        case 6: return dpp<0x156>(v);
+        case 7: return dpp<0x157>(v);
+        case 8: return dpp<0x158>(v);
+        case 9: return dpp<0x159>(v);
+        case 10: return dpp<0x15A>(v);
+        case 11: return dpp<0x15B>(v);
+        case 12: return dpp<0x15C>(v);
+        case 13: return dpp<0x15D>(v);
+        case 14: return dpp<0x15E>(v);
+        default: return dpp<0x15F>(v);
+    }
+}
+
+__device__ __forceinline__ int perm_at(uint64_t perm, int k) { return (int)((perm >> (4 * k)) & 15); }
+
 __device__ void factor_real(LUR &F, const GL &L, int r, int N) {
     bool used = r >= N;
-    F.pos = -1;
     F.perm = 0;
-    F.dinv = 0.0;
+    double dinv = 0.0;
 #pragma unroll
     for (int k = 0; k < G; ++k) {
         if (k < N) {
-            const double v = used ? -1.0 : fabs(F.a[k]);
-            const int p = gargmax(v, r);
+            const int p = gpivot(fabs(F.a[k]), used, r);
             F.perm |= (uint64_t)p << (4 * k);
             if (r == p) {
                 used = true;
-                F.pos = k;
-                F.dinv = 1.0 / F.a[k];
+                dinv = 1.0 / F.a[k];
 #pragma unroll
-                for (int c = 0; c < G; ++c) L.prow[c] = F.a[c];
+                for (int c = k; c < G; ++c) L.prow[c] = F.a[c];
             }
             sync_wave();
             if (!used) {
-                const double l = F.a[k] * (1.0 / L.prow[k]);
+                const double l = F.a[k] / L.prow[k];
                 F.a[k] = l;
 #pragma unroll
                 for (int c = k + 1; c < G; ++c) F.a[c] -= l * L.prow[c];
@@ -349,27 +397,29 @@ __device__ void factor_real(LUR &F, const GL &L, int r, int N) {
             sync_wave();
         }
     }
+    // lane k takes the row that became pivot at step k
+    const int src = r < N ? perm_at(F.perm, r) : r;
+#pragma unroll
+    for (int c = 0; c < G; ++c) F.a[c] = gb(F.a[c], src);
+    F.dinv = gb(dinv, src);
 }
 
 __device__ void factor_cplx(LUC &F, const GL &L, int r, int N) {
     bool used = r >= N;
-    F.pos = -1;
     F.perm = 0;
-    F.dr = F.di = 0.0;
+    double dr = 0.0, di = 0.0;
 #pragma unroll
     for (int k = 0; k < G; ++k) {
         if (k < N) {
-            const double v = used ? -1.0 : F.re[k] * F.re[k] + F.im[k] * F.im[k];
-            const int p = gargmax(v, r);
+            const int p = gpivot(F.re[k] * F.re[k] + F.im[k] * F.im[k], used, r);
             F.perm |= (uint64_t)p << (4 * k);
             if (r == p) {
                 used = true;
-                F.pos = k;
                 const double dd = 1.0 / (F.re[k] * F.re[k] + F.im[k] * F.im[k]);
-                F.dr = F.re[k] * dd;
-                F.di = -F.im[k] * dd;
+                dr = F.re[k] * dd;
+                di = -F.im[k] * dd;
 #pragma unroll
-                for (int c = 0; c < G; ++c) { L.prow[c] = F.re[c]; L.prow[G + c] = F.im[c]; }
+                for (int c = k; c < G; ++c) { L.prow[c] = F.re[c]; L.prow[G + c] = F.im[c]; }
             }
             sync_wave();
             if (!used) {
@@ -390,37 +440,43 @@ __device__ void factor_cplx(LUC &F, const GL &L, int r, int N) {
             sync_wave();
         }
     }
+    const int src = r < N ? perm_at(F.perm, r) : r;
+#pragma unroll
+    for (int c = 0; c < G; ++c) {
+        F.re[c] = gb(F.re[c], src);
+        F.im[c] = gb(F.im[c], src);
+    }
+    F.dr = gb(dr, src);
+    F.di = gb(di, src);
 }
 
-// solve with the factors: b (component r in lane r) -> x (component r in lane r)
+// x = E^-1 b, component r in lane r in and out
 __device__ double solve_real(const LUR &F, int r, int N, double b) {
-    double acc = b;
+    double acc = gb(b, r < N ? perm_at(F.perm, r) : r);        // P b
 #pragma unroll
     for (int k = 0; k < G; ++k)
         if (k < N) {
-            const double yk = gb(acc, (int)((F.perm >> (4 * k)) & 15));
-            if (F.pos > k) acc -= F.a[k] * yk;
+            const double yk = bcast(acc, k);
+            if (r > k) acc -= F.a[k] * yk;
         }
 #pragma unroll
     for (int k = G - 1; k >= 0; --k)
         if (k < N) {
-            if (F.pos == k) acc *= F.dinv;
-            const double xk = gb(acc, (int)((F.perm >> (4 * k)) & 15));
-            if (F.pos >= 0 && F.pos < k) acc -= F.a[k] * xk;
+            if (r == k) acc *= F.dinv;
+            const double xk = bcast(acc, k);
+            if (r < k) acc -= F.a[k] * xk;
         }
-    const int src = r < N ? (int)((F.perm >> (4 * r)) & 15) : r;
-    const double x = gb(acc, src);
-    return r < N ? x : 0.0;
+    return r < N ? acc : 0.0;
 }
 
 __device__ void solve_cplx(const LUC &F, int r, int N, double &br, double &bi) {
-    double ar = br, ai = bi;
+    const int src = r < N ? perm_at(F.perm, r) : r;
+    double ar = gb(br, src), ai = gb(bi, src);
 #pragma unroll
     for (int k = 0; k < G; ++k)
         if (k < N) {
-            const int p = (int)((F.perm >> (4 * k)) & 15);
-            const double yr = gb(ar, p), yi = gb(ai, p);
-            if (F.pos > k) {
+            const double yr = bcast(ar, k), yi = bcast(ai, k);
+            if (r > k) {
                 ar -= F.re[k] * yr - F.im[k] * yi;
                 ai -= F.re[k] * yi + F.im[k] * yr;
             }
@@ -428,22 +484,19 @@ __device__ void solve_cplx(const LUC &F, int r, int N, double &br, double &bi) {
 #pragma unroll
     for (int k = G - 1; k >= 0; --k)
         if (k < N) {
-            if (F.pos == k) {
+            if (r == k) {
                 const double tr = ar * F.dr - ai * F.di;
                 ai = ar * F.di + ai * F.dr;
                 ar = tr;
             }
-            const int p = (int)((F.perm >> (4 * k)) & 15);
-            const double xr = gb(ar, p), xi = gb(ai, p);
-            if (F.pos >= 0 && F.pos < k) {
+            const double xr = bcast(ar, k), xi = bcast(ai, k);
+            if (r < k) {
                 ar -= F.re[k] * xr - F.im[k] * xi;
                 ai -= F.re[k] * xi + F.im[k] * xr;
             }
         }
-    const int src = r < N ? (int)((F.perm >> (4 * r)) & 15) : r;
-    const double xr = gb(ar, src), xi = gb(ai, src);
-    br = r < N ? xr : 0.0;
-    bi = r < N ? xi : 0.0;
+    br = r < N ? ar : 0.0;
+    bi = r < N ? ai : 0.0;
 }
 
 enum { ACT_JAC = 0, ACT_LU = 1, ACT_SAME = 2 };
