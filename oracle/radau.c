@@ -375,7 +375,7 @@ static int radau_core(const problem *pb, double dt, double *y, double atol, doub
             res->nfev++;
             if (reject) hnew = fmin(hnew, h);
             reject = 0;
-            if (t + hnew >= dt) {
+            if (t + 1.0001 * hnew >= dt) {   /* last step: no tail shorter than 1e-4 h */
                 h = dt - t;
                 last = 1;
             } else {

@@ -503,6 +503,12 @@ enum { ACT_JAC = 0, ACT_LU = 1, ACT_SAME = 2 };
 
 __global__ void reset_queue_kernel(int *q) { *q = 0; }
 
+// One step attempt per group per loop iteration: the groups of a wavefront run
+// the same sequence of phases (refill, Jacobian, factorisation, Newton, error
+// estimate, control) with per-group masks, and a group whose state is done
+// takes the next state from the queue in the next iteration without waiting
+// for the other groups of its wavefront.  The wavefront leaves the loop when
+// no group holds a state.
 __global__ __launch_bounds__(64) void radau_group_kernel(DevMech m, RadauParams rp, int64_t n,
                                                          const double *__restrict__ yin, double *__restrict__ yout,
                                                          int32_t *__restrict__ cnt, int *__restrict__ queue,
@@ -518,127 +524,161 @@ __global__ __launch_bounds__(64) void radau_group_kernel(DevMech m, RadauParams 
 
     LUR E1;
     LUC E2;
+    bool have = false, drained = false;
+    int64_t s = 0;
+    double P = 0.0, y = 0.0, f0 = 0.0, sc = 1.0, t = 0.0, h = 0.0;
+    double eta = 1.0, theta = 1.0, hacc = 0.0, erracc = 1e-2, hlast = 0.0;
+    double Zs1 = 0.0, Zs2 = 0.0, Zs3 = 0.0;
+    bool last = false, first = true, reject = false, jac_fresh = false;
+    int action = ACT_JAC;
+    int status = 0, nstep = 0, nacc = 0, nrej = 0, nnewt = 0, nnf = 0, nfev = 0, njev = 0, nlu = 0;
+
     for (;;) {
-        int qi = 0;
-        if (r == 0) qi = atomicAdd(queue, 1);
-        qi = gbi(qi, 0);
-        if (qi >= n) break;
-        const int64_t s = order ? (int64_t)order[qi] : (int64_t)qi;
-
-        const double P = yin[(size_t)(K + 1) * n + s];
-        double y = comp ? yin[(size_t)r * n + s] : 0.0;
-        const double bad_l = (comp && !isfinite(y)) || (r == 0 && !(y > 0.0)) || (r == 0 && !(P > 0.0 && isfinite(P)));
-        const bool bad = gsum(bad_l ? 1.0 : 0.0) > 0.0;
-        int status = RK_ST_OK, nstep = 0, nacc = 0, nrej = 0, nnewt = 0, nnf = 0, nfev = 0, njev = 0, nlu = 0;
-        if (bad) {
-            status = RK_ST_NONFINITE;
-            if (comp) yout[(size_t)r * n + s] = y;
-            if (r == 0) yout[(size_t)(K + 1) * n + s] = P;
-        } else {
-            double t = 0.0, h = rp.h0;
-            bool last = false;
-            if (t + 1.0001 * h >= dt) { h = dt - t; last = true; }
-            double f0 = rhs_g(m, L, r, y, P);
-            ++nfev;
-            double sc = comp ? atol + rtol * fabs(y) : 1.0;
-            bool first = true, reject = false, jac_fresh = false;
-            double eta = 1.0, theta = 1.0, hacc = h, erracc = 1e-2, hlast = h;
-            double Zs1 = 0.0, Zs2 = 0.0, Zs3 = 0.0;
-            int action = ACT_JAC;
-            for (;;) {
-                if (action == ACT_JAC) {
-                    jac_g(m, L, r, y, P);
-                    ++njev;
-                    jac_fresh = true;
-                    action = ACT_LU;
-                }
-                if (action == ACT_LU) {
-                    const double gh = rp.g / h, ah = rp.a / h, bh = rp.b / h;
-                    const double *row = L.J + r * G;
-#pragma unroll
-                    for (int c = 0; c < G; ++c) {
-                        const double j = comp ? row[c] : 0.0;
-                        E1.a[c] = -j;
-                        E2.re[c] = -j;
-                        E2.im[c] = 0.0;
+        // ---- refill: take the next state of the queue --------------------------
+        if (!have && !drained) {
+            int qi = 0;
+            if (r == 0) qi = atomicAdd(queue, 1);
+            qi = gbi(qi, 0);
+            if (qi >= n) {
+                drained = true;
+            } else {
+                s = order ? (int64_t)order[qi] : (int64_t)qi;
+                P = yin[(size_t)(K + 1) * n + s];
+                y = comp ? yin[(size_t)r * n + s] : 0.0;
+                const bool bad_l = (comp && !isfinite(y)) || (r == 0 && !(y > 0.0)) ||
+                                   (r == 0 && !(P > 0.0 && isfinite(P)));
+                nstep = nacc = nrej = nnewt = nnf = nfev = njev = nlu = 0;
+                if (gsum(bad_l ? 1.0 : 0.0) > 0.0) {
+                    status = RK_ST_NONFINITE;
+                    if (comp) yout[(size_t)r * n + s] = y;
+                    if (r == 0) yout[(size_t)(K + 1) * n + s] = P;
+                    if (r == 0) {
+                        cnt[(size_t)C_STATUS * n + s] = status;
+                        for (int c = 1; c < kNumCounters; ++c) cnt[(size_t)c * n + s] = 0;
                     }
-#pragma unroll
-                    for (int c = 0; c < G; ++c)
-                        if (c == r) { E1.a[c] += gh; E2.re[c] += ah; E2.im[c] = bh; }
-                    sync_wave();
-                    factor_real(E1, L, r, N);
-                    factor_cplx(E2, L, r, N);
-                    ++nlu;
-                }
-                action = ACT_SAME;
-                if (nstep >= rp.nmax) { status = RK_ST_STEP_LIMIT; break; }
-                if (h < rp.hmin) { status = RK_ST_H_UNDERFLOW; break; }
-                ++nstep;
-
-                // starting values (collocation polynomial of the previous step)
-                double Z1, Z2, Z3;
-                if (first) {
-                    Z1 = Z2 = Z3 = 0.0;
                 } else {
-                    const double c1 = rp.c1, c2 = rp.c2, q = h / hlast;
-                    const double t1 = 1.0 + c1 * q, t2 = 1.0 + c2 * q, t3 = 1.0 + q;
-                    const double d01 = Zs1 / c1, d12 = (Zs2 - Zs1) / (c2 - c1), d23 = (Zs3 - Zs2) / (1.0 - c2);
-                    const double d012 = (d12 - d01) / c2, d123 = (d23 - d12) / (1.0 - c1);
-                    const double d0123 = d123 - d012;
-                    Z1 = t1 * (d01 + (t1 - c1) * (d012 + (t1 - c2) * d0123)) - Zs3;
-                    Z2 = t2 * (d01 + (t2 - c1) * (d012 + (t2 - c2) * d0123)) - Zs3;
-                    Z3 = t3 * (d01 + (t3 - c1) * (d012 + (t3 - c2) * d0123)) - Zs3;
-                }
-                double W1 = rp.Ti[0] * Z1 + rp.Ti[1] * Z2 + rp.Ti[2] * Z3;
-                double W2 = rp.Ti[3] * Z1 + rp.Ti[4] * Z2 + rp.Ti[5] * Z3;
-                double W3 = rp.Ti[6] * Z1 + rp.Ti[7] * Z2 + rp.Ti[8] * Z3;
-
-                eta = pow(fmax(eta, kU), 0.8);
-                bool converged = false;
-                int newt = 0;
-                double dn_old = 1.0;
-                for (int it = 1; it <= kmax; ++it) {
-                    const double F1 = rhs_g(m, L, r, y + Z1, P);
-                    const double F2 = rhs_g(m, L, r, y + Z2, P);
-                    const double F3 = rhs_g(m, L, r, y + Z3, P);
-                    nfev += 3;
-                    const double gh = rp.g / h, ah = rp.a / h, bh = rp.b / h;
-                    const double G1 = rp.Ti[0] * F1 + rp.Ti[1] * F2 + rp.Ti[2] * F3;
-                    const double G2 = rp.Ti[3] * F1 + rp.Ti[4] * F2 + rp.Ti[5] * F3;
-                    const double G3 = rp.Ti[6] * F1 + rp.Ti[7] * F2 + rp.Ti[8] * F3;
-                    double dW1 = comp ? G1 - gh * W1 : 0.0;
-                    double dW2 = comp ? G2 - (ah * W2 - bh * W3) : 0.0;
-                    double dW3 = comp ? G3 - (bh * W2 + ah * W3) : 0.0;
-                    dW1 = solve_real(E1, r, N, dW1);
-                    solve_cplx(E2, r, N, dW2, dW3);
-                    const double dZ1 = rp.T[0] * dW1 + rp.T[1] * dW2 + rp.T[2] * dW3;
-                    const double dZ2 = rp.T[3] * dW1 + rp.T[4] * dW2 + rp.T[5] * dW3;
-                    const double dZ3 = rp.T[6] * dW1 + rp.T[7] * dW2 + rp.T[8] * dW3;
-                    ++nnewt;
-                    newt = it;
-                    const double dn = sqrt(gsum(comp ? (dZ1 * dZ1 + dZ2 * dZ2 + dZ3 * dZ3) / (sc * sc) : 0.0) / (3 * N));
-                    if (!isfinite(dn)) break;
-                    if (it >= 2) {
-                        const double th = dn / dn_old;
-                        theta = th;
-                        if (th >= 0.99) break;
-                        eta = th / (1.0 - th);
-                        if (pow(th, (double)(kmax - it)) / (1.0 - th) * dn > kappa) break;
-                    }
-                    dn_old = fmax(dn, kU);
-                    Z1 += dZ1; Z2 += dZ2; Z3 += dZ3;
-                    W1 += dW1; W2 += dW2; W3 += dW3;
-                    if (eta * dn <= kappa) { converged = true; break; }
-                }
-                if (!converged) {
-                    ++nnf;
-                    h *= 0.5;
-                    reject = true;
+                    have = true;
+                    status = RK_ST_OK;
+                    t = 0.0;
+                    h = rp.h0;
                     last = false;
-                    action = jac_fresh ? ACT_LU : ACT_JAC;
-                    continue;
+                    if (t + 1.0001 * h >= dt) { h = dt - t; last = true; }
+                    f0 = rhs_g(m, L, r, y, P);
+                    nfev = 1;
+                    sc = comp ? atol + rtol * fabs(y) : 1.0;
+                    first = true;
+                    reject = false;
+                    jac_fresh = false;
+                    eta = 1.0;
+                    theta = 1.0;
+                    hacc = h;
+                    erracc = 1e-2;
+                    hlast = h;
+                    Zs1 = Zs2 = Zs3 = 0.0;
+                    action = ACT_JAC;
                 }
+            }
+        }
+        if (__ballot(have) == 0ull && __ballot(!drained) == 0ull) break;
+        if (!have) continue;
 
+        // ---- one step attempt ---------------------------------------------------
+        if (action == ACT_JAC) {
+            jac_g(m, L, r, y, P);
+            ++njev;
+            jac_fresh = true;
+            action = ACT_LU;
+        }
+        if (action == ACT_LU) {
+            const double gh = rp.g / h, ah = rp.a / h, bh = rp.b / h;
+            const double *row = L.J + r * G;
+#pragma unroll
+            for (int c = 0; c < G; ++c) {
+                const double j = comp ? row[c] : 0.0;
+                E1.a[c] = -j;
+                E2.re[c] = -j;
+                E2.im[c] = 0.0;
+            }
+#pragma unroll
+            for (int c = 0; c < G; ++c)
+                if (c == r) { E1.a[c] += gh; E2.re[c] += ah; E2.im[c] = bh; }
+            sync_wave();
+            factor_real(E1, L, r, N);
+            factor_cplx(E2, L, r, N);
+            ++nlu;
+        }
+        action = ACT_SAME;
+        bool done = false;
+        if (nstep >= rp.nmax) {
+            status = RK_ST_STEP_LIMIT;
+            done = true;
+        } else if (h < rp.hmin) {
+            status = RK_ST_H_UNDERFLOW;
+            done = true;
+        } else {
+            ++nstep;
+            // starting values (collocation polynomial of the previous step)
+            double Z1, Z2, Z3;
+            if (first) {
+                Z1 = Z2 = Z3 = 0.0;
+            } else {
+                const double c1 = rp.c1, c2 = rp.c2, q = h / hlast;
+                const double t1 = 1.0 + c1 * q, t2 = 1.0 + c2 * q, t3 = 1.0 + q;
+                const double d01 = Zs1 / c1, d12 = (Zs2 - Zs1) / (c2 - c1), d23 = (Zs3 - Zs2) / (1.0 - c2);
+                const double d012 = (d12 - d01) / c2, d123 = (d23 - d12) / (1.0 - c1);
+                const double d0123 = d123 - d012;
+                Z1 = t1 * (d01 + (t1 - c1) * (d012 + (t1 - c2) * d0123)) - Zs3;
+                Z2 = t2 * (d01 + (t2 - c1) * (d012 + (t2 - c2) * d0123)) - Zs3;
+                Z3 = t3 * (d01 + (t3 - c1) * (d012 + (t3 - c2) * d0123)) - Zs3;
+            }
+            double W1 = rp.Ti[0] * Z1 + rp.Ti[1] * Z2 + rp.Ti[2] * Z3;
+            double W2 = rp.Ti[3] * Z1 + rp.Ti[4] * Z2 + rp.Ti[5] * Z3;
+            double W3 = rp.Ti[6] * Z1 + rp.Ti[7] * Z2 + rp.Ti[8] * Z3;
+
+            eta = pow(fmax(eta, kU), 0.8);
+            bool converged = false;
+            int newt = 0;
+            double dn_old = 1.0;
+            for (int it = 1; it <= kmax; ++it) {
+                const double F1 = rhs_g(m, L, r, y + Z1, P);
+                const double F2 = rhs_g(m, L, r, y + Z2, P);
+                const double F3 = rhs_g(m, L, r, y + Z3, P);
+                nfev += 3;
+                const double gh = rp.g / h, ah = rp.a / h, bh = rp.b / h;
+                const double G1 = rp.Ti[0] * F1 + rp.Ti[1] * F2 + rp.Ti[2] * F3;
+                const double G2 = rp.Ti[3] * F1 + rp.Ti[4] * F2 + rp.Ti[5] * F3;
+                const double G3 = rp.Ti[6] * F1 + rp.Ti[7] * F2 + rp.Ti[8] * F3;
+                double dW1 = comp ? G1 - gh * W1 : 0.0;
+                double dW2 = comp ? G2 - (ah * W2 - bh * W3) : 0.0;
+                double dW3 = comp ? G3 - (bh * W2 + ah * W3) : 0.0;
+                dW1 = solve_real(E1, r, N, dW1);
+                solve_cplx(E2, r, N, dW2, dW3);
+                const double dZ1 = rp.T[0] * dW1 + rp.T[1] * dW2 + rp.T[2] * dW3;
+                const double dZ2 = rp.T[3] * dW1 + rp.T[4] * dW2 + rp.T[5] * dW3;
+                const double dZ3 = rp.T[6] * dW1 + rp.T[7] * dW2 + rp.T[8] * dW3;
+                ++nnewt;
+                newt = it;
+                const double dn = sqrt(gsum(comp ? (dZ1 * dZ1 + dZ2 * dZ2 + dZ3 * dZ3) / (sc * sc) : 0.0) / (3 * N));
+                if (!isfinite(dn)) break;
+                if (it >= 2) {
+                    const double th = dn / dn_old;
+                    theta = th;
+                    if (th >= 0.99) break;
+                    eta = th / (1.0 - th);
+                    if (pow(th, (double)(kmax - it)) / (1.0 - th) * dn > kappa) break;
+                }
+                dn_old = fmax(dn, kU);
+                Z1 += dZ1; Z2 += dZ2; Z3 += dZ3;
+                W1 += dW1; W2 += dW2; W3 += dW3;
+                if (eta * dn <= kappa) { converged = true; break; }
+            }
+            if (!converged) {
+                ++nnf;
+                h *= 0.5;
+                reject = true;
+                last = false;
+                action = jac_fresh ? ACT_LU : ACT_JAC;
+            } else {
                 // embedded error estimate
                 const double invh = 1.0 / h;
                 const double dz = (rp.d[0] * Z1 + rp.d[1] * Z2 + rp.d[2] * Z3) * invh;
@@ -673,20 +713,27 @@ __global__ __launch_bounds__(64) void radau_group_kernel(DevMech m, RadauParams 
                     sc = comp ? atol + rtol * fabs(y) : 1.0;
                     t = last ? dt : t + h;
                     jac_fresh = false;
-                    if (last) break;
-                    f0 = rhs_g(m, L, r, y, P);
-                    ++nfev;
-                    if (reject) hnew = fmin(hnew, h);
-                    reject = false;
-                    if (t + hnew >= dt) {
-                        h = dt - t;
-                        last = true;
+                    if (last) {
+                        done = true;
                     } else {
-                        const double qt = hnew / h;
-                        if (theta <= 1e-3 && qt >= 1.0 && qt <= 1.2) { action = ACT_SAME; continue; }
-                        h = hnew;
+                        f0 = rhs_g(m, L, r, y, P);
+                        ++nfev;
+                        if (reject) hnew = fmin(hnew, h);
+                        reject = false;
+                        if (t + 1.0001 * hnew >= dt) {   // last step: no tail shorter than 1e-4 h
+                            h = dt - t;
+                            last = true;
+                            action = theta <= 1e-3 ? ACT_LU : ACT_JAC;
+                        } else {
+                            const double qt = hnew / h;
+                            if (theta <= 1e-3 && qt >= 1.0 && qt <= 1.2) {
+                                action = ACT_SAME;
+                            } else {
+                                h = hnew;
+                                action = theta <= 1e-3 ? ACT_LU : ACT_JAC;
+                            }
+                        }
                     }
-                    action = theta <= 1e-3 ? ACT_LU : ACT_JAC;
                 } else {
                     ++nrej;
                     reject = true;
@@ -695,19 +742,22 @@ __global__ __launch_bounds__(64) void radau_group_kernel(DevMech m, RadauParams 
                     action = jac_fresh ? ACT_LU : ACT_JAC;
                 }
             }
-            if (comp) yout[(size_t)r * n + s] = y;
-            if (r == 0) yout[(size_t)(K + 1) * n + s] = P;
         }
-        if (r == 0) {
-            cnt[(size_t)C_STATUS * n + s] = status;
-            cnt[(size_t)C_NSTEP * n + s] = nstep;
-            cnt[(size_t)C_NACC * n + s] = nacc;
-            cnt[(size_t)C_NREJ * n + s] = nrej;
-            cnt[(size_t)C_NNEWT * n + s] = nnewt;
-            cnt[(size_t)C_NNFAIL * n + s] = nnf;
-            cnt[(size_t)C_NFEV * n + s] = nfev;
-            cnt[(size_t)C_NJEV * n + s] = njev;
-            cnt[(size_t)C_NLU * n + s] = nlu;
+        if (done) {
+            if (comp) yout[(size_t)r * n + s] = y;
+            if (r == 0) {
+                yout[(size_t)(K + 1) * n + s] = P;
+                cnt[(size_t)C_STATUS * n + s] = status;
+                cnt[(size_t)C_NSTEP * n + s] = nstep;
+                cnt[(size_t)C_NACC * n + s] = nacc;
+                cnt[(size_t)C_NREJ * n + s] = nrej;
+                cnt[(size_t)C_NNEWT * n + s] = nnewt;
+                cnt[(size_t)C_NNFAIL * n + s] = nnf;
+                cnt[(size_t)C_NFEV * n + s] = nfev;
+                cnt[(size_t)C_NJEV * n + s] = njev;
+                cnt[(size_t)C_NLU * n + s] = nlu;
+            }
+            have = false;
         }
     }
 }

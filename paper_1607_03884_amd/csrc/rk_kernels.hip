@@ -595,7 +595,7 @@ __global__ __launch_bounds__(64) void radau_lane_kernel(DevMech m, LaneLayout L,
                 ++nfev;
                 if (reject) hnew = fmin(hnew, h);
                 reject = false;
-                if (t + hnew >= dt) {
+                if (t + 1.0001 * hnew >= dt) {   // last step: no tail shorter than 1e-4 h
                     h = dt - t;
                     last = true;
                 } else {

@@ -183,6 +183,11 @@ def test_cfg1_full_size_sampled(torch_dev, gm13, m13, dt, variant):
     got, st = _run(torch_dev, gm13, rows, dt, variant=variant)
     gm13.set_option("variant", "lane")
     status = st["per_state_status"]
+    if not np.all(status == 0):
+        badi = np.nonzero(status)[0]
+        ref, res = m13.integrate(rows[badi[:8]], dt)
+        print(f"status counts {np.bincount(status)}; failing states {badi[:8]}, gpu steps "
+              f"{st['per_state_steps'][badi[:8]]}, oracle status {res['status']} steps {res['nstep']}")
     assert np.all(status == 0)
     assert np.all(np.isfinite(got))
     assert np.abs(got[:, 1:14].sum(1) - rows[:, 1:14].sum(1)).max() <= 1e-12
