@@ -21,6 +21,29 @@ if ROOT not in sys.path:
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CUs x 64 FP64 FMA/clk x 2 flops x 2.4 GHz
 
+KERNEL_SOURCES = {"radau_group_kernel": ["rk_group.hip", "rk_internal.h"],
+                  "radau_lane_kernel": ["rk_kernels.hip", "rk_internal.h"]}
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per dispatch from the committed counter summary, if it was taken
+    on the current kernel source (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}.md")
+    if not os.path.exists(path) or kernel not in KERNEL_SOURCES:
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and line.split(":")[0] in ("traffic_bytes_per_dispatch", "source_sha256_16"):
+            k, v = line.split(":", 1)
+            fields[k] = v.strip()
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        h.update(open(os.path.join(ROOT, "paper_1607_03884_amd", "csrc", f), "rb").read())
+    if fields.get("source_sha256_16") != h.hexdigest()[:16] or "traffic_bytes_per_dispatch" not in fields:
+        return None
+    return float(fields["traffic_bytes_per_dispatch"])
+
 
 def main() -> int:
     ap = argparse.ArgumentParser()
@@ -31,6 +54,8 @@ def main() -> int:
     ap.add_argument("--variant", default="wave")
     ap.add_argument("--cpu-sample", type=int, default=16384)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="after timing, run one plain 512 MiB device copy (counter calibration)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -82,6 +107,15 @@ def main() -> int:
     kernel_ms = {dt: float(np.mean([a.elapsed_time(b) for a, b in events[dt]])) for dt in wl.dts}
     print(f"[bench] timed {args.steps} steps: {sec_per_step * 1e3:.2f} ms/step", flush=True)
 
+    if args.calib_copy:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print("[bench] calibration copy: 536870912 bytes read, 536870912 bytes written", flush=True)
+        del src, dst
+
     # counters of one (identical, deterministic) launch per dt, outside the timed region
     costs = Costs.of(mech_def)
     per_dt = {}
@@ -101,9 +135,10 @@ def main() -> int:
                              "failed": st["n_failed"], "D64_mean": st["d_mean64"], "D32_mean": st["d_mean32"],
                              "gflop": fl["flops"] / 1e9, "gtrans": fl["transcendentals"] / 1e9}
     achieved = tot_flops / (tot_ms * 1e-3) / 1e12
+    kname = {"lane": "radau_lane_kernel", "wave": "radau_group_kernel"}.get(args.variant, args.variant)
     roofline = {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
-                "kernel": {"lane": "radau_lane_kernel", "wave": "radau_group_kernel"}.get(args.variant, args.variant), "flops_per_launch": tot_flops / len(wl.dts)}
+                "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": measured_traffic(kname, wl.name),
+                "kernel": kname, "flops_per_launch": tot_flops / len(wl.dts)}
 
     cpu = None
     parity = None
