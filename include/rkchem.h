@@ -61,6 +61,9 @@ typedef struct rk_stats {
     int64_t d_hist32[20];
     double d_mean64, d_mean32;
     double kernel_ms;         /* device time of the last call (HIP events) */
+    int64_t fp32_fallback;    /* states the mixed variant re-ran with FP64 factors */
+    int32_t nbins_used;       /* cost bins of the work queue (0: input order) */
+    int32_t grid_used;        /* blocks launched for the integrator */
 } rk_stats;
 
 /* mech_load — read a mechanism file and upload it to the current device.
@@ -106,7 +109,22 @@ int stats_get(rk_mech *mech, rk_stats *out, int32_t *per_state_steps, int32_t *p
  *   "variant"  "auto" (default: "wave" when K + 1 <= 16, else "lane") |
  *              "lane" (one lane per state, the paper's per-thread pattern) |
  *              "wave" (16 lanes of a wavefront cooperate on one state, the
- *              paper's per-block pattern; persistent work queue; K + 1 <= 16)
+ *              paper's per-block pattern; persistent work queue; K + 1 <= 16) |
+ *              "mixed" (as "wave" with the iteration matrices equilibrated and
+ *              factored in FP32; source terms, residuals, error estimate
+ *              (plus one FP64-residual refinement) and control in FP64; a
+ *              state whose Newton iteration diverges twice in a row after
+ *              its first accepted step is
+ *              re-integrated from its initial value with FP64 factors)
+ *   "binning"  number of cost bins (0..64, default 0): one source-term
+ *              evaluation per state gives the key ||dt f(y0)|| (RMS in the
+ *              error weights); states are queued costliest bin first
+ *   "grid_pct" share of the resident capacity launched for the persistent
+ *              kernels (10..100, default 100)
+ *   "autotune" "1": on the first call per dt, time the integrator on the first
+ *              min(n, 32768) states for bins in {0, 8, 16, 32} and grid in
+ *              {100 %, 50 %}, keep the fastest (this call blocks the host);
+ *              "0": forget the choices
  *   "kmax"     max Newton iterations per step (default 7)
  *   "kappa"    Newton stopping constant (default max(10u/rtol, min(0.03, rtol^0.5)))
  *   "nmax"     step-attempt limit per state (default 100000)

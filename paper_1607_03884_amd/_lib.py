@@ -25,7 +25,8 @@ class RkStats(ctypes.Structure):
                 ("f_evals", ctypes.c_int64), ("jac_evals", ctypes.c_int64), ("lu_factor", ctypes.c_int64),
                 ("n_failed", ctypes.c_int64), ("max_steps", ctypes.c_int32), ("min_steps", ctypes.c_int32),
                 ("d_hist64", ctypes.c_int64 * 20), ("d_hist32", ctypes.c_int64 * 20),
-                ("d_mean64", ctypes.c_double), ("d_mean32", ctypes.c_double), ("kernel_ms", ctypes.c_double)]
+                ("d_mean64", ctypes.c_double), ("d_mean32", ctypes.c_double), ("kernel_ms", ctypes.c_double),
+                ("fp32_fallback", ctypes.c_int64), ("nbins_used", ctypes.c_int32), ("grid_used", ctypes.c_int32)]
 
 
 EXPORTS = ["mech_load", "mech_free", "mech_dims", "radau_integrate", "stats_get", "radau_set_option",

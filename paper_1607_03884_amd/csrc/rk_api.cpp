@@ -361,6 +361,32 @@ int ensure_workspace(rk_mech *m, int64_t n) {
         (void)hipGetLastError();
         return fail(RK_ENOMEM, "cannot allocate the work queue");
     }
+    if (n > m->fb_cap) {
+        if (m->fb_list) { (void)hipDeviceSynchronize(); (void)hipFree(m->fb_list); m->fb_list = nullptr; m->fb_cap = 0; }
+        if (hipMalloc(&m->fb_list, (size_t)n * sizeof(int)) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(RK_ENOMEM, "cannot allocate the fallback list");
+        }
+        m->fb_cap = n;
+    }
+    if (m->nbins > 0 || m->autotune) {
+        if (n > m->bin_cap) {
+            if (m->bins) { (void)hipDeviceSynchronize(); (void)hipFree(m->bins); (void)hipFree(m->order); }
+            m->bins = m->order = nullptr;
+            m->bin_cap = 0;
+            if (hipMalloc(&m->bins, (size_t)n * sizeof(int)) != hipSuccess ||
+                hipMalloc(&m->order, (size_t)n * sizeof(int)) != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(RK_ENOMEM, "cannot allocate the binning workspace");
+            }
+            m->bin_cap = n;
+        }
+        if (!m->hist && (hipMalloc(&m->hist, 128 * sizeof(int)) != hipSuccess ||
+                         hipMalloc(&m->proxy_scratch, rk::proxy_scratch_doubles(m->K) * sizeof(double)) != hipSuccess)) {
+            (void)hipGetLastError();
+            return fail(RK_ENOMEM, "cannot allocate the binning workspace");
+        }
+    }
     if (n > m->counters_cap) {
         if (m->counters) { (void)hipDeviceSynchronize(); (void)hipFree(m->counters); m->counters = nullptr; m->counters_cap = 0; }
         if (hipMalloc(&m->counters, (size_t)n * rk::kNumCounters * sizeof(int32_t)) != hipSuccess) {
@@ -369,6 +395,76 @@ int ensure_workspace(rk_mech *m, int64_t n) {
         }
         m->counters_cap = n;
     }
+    return RK_OK;
+}
+
+// Enqueue the flag clear, the optional cost binning and the integrator.
+hipError_t launch_integrator(rk_mech *m, const rk::RadauParams &p, int64_t n, const double *yin, double *yout,
+                             double atol, double rtol, int variant, int nbins, int gpct, hipStream_t st) {
+    hipError_t e = rk::launch_zero_i32(m->counters + (size_t)rk::C_FLAGS * n, n, st);
+    if (e != hipSuccess) return e;
+    const int *order = nullptr;
+    if (nbins > 0) {
+        e = rk::launch_binning(m->dev, n, yin, p.dt, atol, rtol, nbins, m->bins, m->order, m->hist, m->proxy_scratch, st);
+        if (e != hipSuccess) return e;
+        order = m->order;
+    }
+    m->last_nbins = nbins;
+    if (variant == 1 || variant == 2) {
+        if (m->group_blocks == 0) m->group_blocks = rk::group_max_blocks(m->R);
+        const int64_t need = (n + 3) / 4;
+        const int64_t cap = std::max<int64_t>(1, (int64_t)m->group_blocks * gpct / 100);
+        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(need, cap));
+        m->last_grid = grid;
+        return rk::launch_radau_group(m->dev, p, n, yin, yout, m->counters, m->queue, m->fb_list, order, variant == 2,
+                                      grid, st);
+    }
+    m->last_grid = (int)((n + rk::kWave - 1) / rk::kWave);
+    return rk::launch_radau_lane(m->dev, p, n, yin, yout, m->scratch, m->counters, order, st);
+}
+
+// Scheduling autotuner: times the integrator on the first min(n, 32768) states
+// (compacted) for every (bin count, persistent-grid size) candidate and keeps
+// the fastest for this dt.  Runs once per (handle, dt); blocks the host.
+int autotune(rk_mech *m, int64_t n, double dt, const double *yin, double atol, double rtol, hipStream_t st,
+             const rk::RadauParams &p, int variant, int &nbins, int &gpct) {
+    for (auto &t : m->tuned)
+        if (t.first == dt) { nbins = t.second.first; gpct = t.second.second; return RK_OK; }
+    const int64_t ms = std::min<int64_t>(n, 32768);
+    const int rows = m->K + 2;
+    const size_t need = (size_t)ms * rows * 2;
+    if (need > m->tune_cap) {
+        if (m->tune_buf) { (void)hipDeviceSynchronize(); (void)hipFree(m->tune_buf); m->tune_buf = nullptr; }
+        if (hipMalloc(&m->tune_buf, need * sizeof(double)) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(RK_ENOMEM, "cannot allocate autotuner buffers");
+        }
+        m->tune_cap = need;
+    }
+    double *ys = m->tune_buf, *yo = m->tune_buf + (size_t)ms * rows;
+    hipError_t e = rk::launch_gather_head(yin, n, ms, rows, ys, st);
+    if (e != hipSuccess) return hip_fail(e, "autotune gather");
+    const int bins_c[] = {0, 8, 16, 32};
+    const int grid_c[] = {100, 50};
+    float best = 1e30f;
+    int bb = 0, bg = 100;
+    for (int b : bins_c)
+        for (int g : grid_c) {
+            if (variant == 0 && g != 100) continue;     // the lane kernel is not persistent
+            for (int rep = 0; rep < 2; ++rep) {         // first run warms caches
+                e = hipEventRecord(m->ev0, st);
+                if (e == hipSuccess) e = launch_integrator(m, p, ms, ys, yo, atol, rtol, variant, b, g, st);
+                if (e == hipSuccess) e = hipEventRecord(m->ev1, st);
+                if (e == hipSuccess) e = hipEventSynchronize(m->ev1);
+                if (e != hipSuccess) return hip_fail(e, "autotune trial");
+            }
+            float ms_t = 0.0f;
+            (void)hipEventElapsedTime(&ms_t, m->ev0, m->ev1);
+            if (ms_t < best) { best = ms_t; bb = b; bg = g; }
+        }
+    m->tuned.push_back({dt, {bb, bg}});
+    nbins = bb;
+    gpct = bg;
     return RK_OK;
 }
 
@@ -407,6 +503,12 @@ void mech_free(rk_mech *m) {
     if (m->scratch) (void)hipFree(m->scratch);
     if (m->counters) (void)hipFree(m->counters);
     if (m->queue) (void)hipFree(m->queue);
+    if (m->fb_list) (void)hipFree(m->fb_list);
+    if (m->bins) (void)hipFree(m->bins);
+    if (m->order) (void)hipFree(m->order);
+    if (m->hist) (void)hipFree(m->hist);
+    if (m->proxy_scratch) (void)hipFree(m->proxy_scratch);
+    if (m->tune_buf) (void)hipFree(m->tune_buf);
     if (m->ev0) (void)hipEventDestroy(m->ev0);
     if (m->ev1) (void)hipEventDestroy(m->ev1);
     delete m;
@@ -426,6 +528,7 @@ int radau_set_option(rk_mech *m, const char *key, const char *value) {
     if (k == "variant") {
         if (v == "lane") m->variant = 0;
         else if (v == "wave") m->variant = 1;
+        else if (v == "mixed") m->variant = 2;
         else if (v == "auto") m->variant = -1;
         else return fail(RK_EINVAL, "unknown variant " + v);
         return RK_OK;
@@ -434,6 +537,24 @@ int radau_set_option(rk_mech *m, const char *key, const char *value) {
         const long x = std::strtol(value, &e, 10);
         if (e == value || *e || x < 1 || x > 100000000) return fail(RK_EINVAL, "bad integer for " + k);
         (k == "kmax" ? m->kmax : m->nmax) = (int)x;
+        return RK_OK;
+    }
+    if (k == "binning") {
+        const long x = std::strtol(value, &e, 10);
+        if (e == value || *e || x < 0 || x > 64) return fail(RK_EINVAL, "binning: number of bins 0..64");
+        m->nbins = (int)x;
+        return RK_OK;
+    }
+    if (k == "grid_pct") {
+        const long x = std::strtol(value, &e, 10);
+        if (e == value || *e || x < 10 || x > 100) return fail(RK_EINVAL, "grid_pct: 10..100");
+        m->grid_pct = (int)x;
+        return RK_OK;
+    }
+    if (k == "autotune") {
+        if (v != "0" && v != "1") return fail(RK_EINVAL, "autotune: 0 or 1");
+        m->autotune = v == "1";
+        if (!m->autotune) m->tuned.clear();
         return RK_OK;
     }
     if (k == "kappa" || k == "h0") {
@@ -455,8 +576,8 @@ int radau_integrate(rk_mech *m, int64_t n, double dt, const double *yin, double 
         return fail(RK_EINVAL, "radau_integrate: state arrays must be device memory");
     const bool group_ok = m->K + 1 <= 16 && rk::group_lds_bytes(m->R) <= 65536;
     const int variant = m->variant >= 0 ? m->variant : (group_ok ? 1 : 0);
-    if (variant == 1 && !group_ok)
-        return fail(RK_EINVAL, "radau_integrate: the wave variant needs K + 1 <= 16 and fewer than 2000 reactions");
+    if ((variant == 1 || variant == 2) && !group_ok)
+        return fail(RK_EINVAL, "radau_integrate: the wave and mixed variants need K + 1 <= 16 and fewer than 2000 reactions");
     int rc = ensure_workspace(m, std::max<int64_t>(n, 1));
     if (rc != RK_OK) return rc;
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -470,16 +591,14 @@ int radau_integrate(rk_mech *m, int64_t n, double dt, const double *yin, double 
     p.kappa = m->kappa > 0.0 ? m->kappa : std::max(10.0 * 2.220446049250313e-16 / rtol, std::min(0.03, std::sqrt(rtol)));
     p.h0 = m->h0 > 0.0 ? m->h0 : std::min(dt, 1e-6);
     p.hmin = 1e-14 * dt;
+    int nbins = m->nbins, gpct = m->grid_pct;
+    if (m->autotune && n >= 4096) {
+        int rc2 = autotune(m, n, dt, yin, atol, rtol, st, p, variant, nbins, gpct);
+        if (rc2 != RK_OK) return rc2;
+    }
     hipError_t e = hipEventRecord(m->ev0, st);
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
-    if (variant == 1) {
-        if (m->group_blocks == 0) m->group_blocks = rk::group_max_blocks(m->R);
-        const int64_t need = (n + 3) / 4;
-        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(need, m->group_blocks));
-        e = rk::launch_radau_group(m->dev, p, n, yin, yout, m->counters, m->queue, nullptr, grid, st);
-    } else {
-        e = rk::launch_radau_lane(m->dev, p, n, yin, yout, m->scratch, m->counters, st);
-    }
+    e = launch_integrator(m, p, n, yin, yout, atol, rtol, variant, nbins, gpct, st);
     if (e != hipSuccess) return hip_fail(e, "radau kernel launch");
     e = hipEventRecord(m->ev1, st);
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
@@ -515,6 +634,7 @@ int stats_get(rk_mech *m, rk_stats *out, int32_t *steps, int32_t *status) {
         out->f_evals += c[(size_t)rk::C_NFEV * n + i];
         out->jac_evals += c[(size_t)rk::C_NJEV * n + i];
         out->lu_factor += c[(size_t)rk::C_NLU * n + i];
+        out->fp32_fallback += c[(size_t)rk::C_FLAGS * n + i] & 1;
         out->n_failed += st[i] != RK_ST_OK;
         out->max_steps = std::max(out->max_steps, ns[i]);
         out->min_steps = std::min(out->min_steps, ns[i]);
@@ -539,6 +659,8 @@ int stats_get(rk_mech *m, rk_stats *out, int32_t *steps, int32_t *status) {
     };
     hist(64, out->d_hist64, &out->d_mean64);
     hist(32, out->d_hist32, &out->d_mean32);
+    out->nbins_used = m->last_nbins;
+    out->grid_used = m->last_grid;
     if (steps) std::memcpy(steps, ns, (size_t)n * sizeof(int32_t));
     if (status) std::memcpy(status, st, (size_t)n * sizeof(int32_t));
     return RK_OK;

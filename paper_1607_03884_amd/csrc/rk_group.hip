@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 #include "rk_internal.h"
 
@@ -335,16 +336,25 @@ __device__ void jac_g(const DevMech &m, const GL &L, int r, double yv, double P)
 // L\U (P E = L U), which lets the substitutions broadcast from lane k with an
 // in-row DPP move.
 // ---------------------------------------------------------------------------
+// S is the storage (and elimination) precision of the factors: double for
+// the plain path, float for the mixed path.  Substitutions run in double.
+// With float factors the matrix is equilibrated first: columns scaled by the
+// error weights sc_c (a similarity with rows 1/sc_r) and rows by their
+// largest entry; rs = row factor of the lane's row, cs = sc of its column.
+template <typename S>
 struct LUR {
-    double a[G];
+    S a[G];
     double dinv;      // 1 / U_kk of the lane's row
     uint64_t perm;    // pivot lane of step k in bits 4k..4k+3
+    double rs, cs;
 };
 
+template <typename S>
 struct LUC {
-    double re[G], im[G];
+    S re[G], im[G];
     double dr, di;    // 1 / U_kk
     uint64_t perm;
+    double rs, cs;
 };
 
 // value of lane k of the 16-lane row (row_newbcast:k); k is a constant once the
@@ -372,27 +382,28 @@ __device__ __forceinline__ double bcast(double v, int k) {
 
 __device__ __forceinline__ int perm_at(uint64_t perm, int k) { return (int)((perm >> (4 * k)) & 15); }
 
-__device__ void factor_real(LUR &F, const GL &L, int r, int N) {
+template <typename S>
+__device__ void factor_real(LUR<S> &F, const GL &L, int r, int N) {
     bool used = r >= N;
     F.perm = 0;
     double dinv = 0.0;
 #pragma unroll
     for (int k = 0; k < G; ++k) {
         if (k < N) {
-            const int p = gpivot(fabs(F.a[k]), used, r);
+            const int p = gpivot(fabs((double)F.a[k]), used, r);
             F.perm |= (uint64_t)p << (4 * k);
             if (r == p) {
                 used = true;
-                dinv = 1.0 / F.a[k];
+                dinv = 1.0 / (double)F.a[k];
 #pragma unroll
-                for (int c = k; c < G; ++c) L.prow[c] = F.a[c];
+                for (int c = k; c < G; ++c) L.prow[c] = (double)F.a[c];
             }
             sync_wave();
             if (!used) {
-                const double l = F.a[k] / L.prow[k];
+                const S l = F.a[k] / (S)L.prow[k];
                 F.a[k] = l;
 #pragma unroll
-                for (int c = k + 1; c < G; ++c) F.a[c] -= l * L.prow[c];
+                for (int c = k + 1; c < G; ++c) F.a[c] -= l * (S)L.prow[c];
             }
             sync_wave();
         }
@@ -404,35 +415,37 @@ __device__ void factor_real(LUR &F, const GL &L, int r, int N) {
     F.dinv = gb(dinv, src);
 }
 
-__device__ void factor_cplx(LUC &F, const GL &L, int r, int N) {
+template <typename S>
+__device__ void factor_cplx(LUC<S> &F, const GL &L, int r, int N) {
     bool used = r >= N;
     F.perm = 0;
     double dr = 0.0, di = 0.0;
 #pragma unroll
     for (int k = 0; k < G; ++k) {
         if (k < N) {
-            const int p = gpivot(F.re[k] * F.re[k] + F.im[k] * F.im[k], used, r);
+            const double mr = F.re[k], mi = F.im[k];
+            const int p = gpivot(mr * mr + mi * mi, used, r);
             F.perm |= (uint64_t)p << (4 * k);
             if (r == p) {
                 used = true;
-                const double dd = 1.0 / (F.re[k] * F.re[k] + F.im[k] * F.im[k]);
-                dr = F.re[k] * dd;
-                di = -F.im[k] * dd;
+                const double dd = 1.0 / (mr * mr + mi * mi);
+                dr = mr * dd;
+                di = -mi * dd;
 #pragma unroll
-                for (int c = k; c < G; ++c) { L.prow[c] = F.re[c]; L.prow[G + c] = F.im[c]; }
+                for (int c = k; c < G; ++c) { L.prow[c] = (double)F.re[c]; L.prow[G + c] = (double)F.im[c]; }
             }
             sync_wave();
             if (!used) {
-                const double pr = L.prow[k], pi = L.prow[G + k];
-                const double dd = 1.0 / (pr * pr + pi * pi);
-                const double ir = pr * dd, ii = -pi * dd;
-                const double xr = F.re[k], xi = F.im[k];
-                const double lr = xr * ir - xi * ii, li = xr * ii + xi * ir;
+                const S pr = (S)L.prow[k], pi = (S)L.prow[G + k];
+                const S dd = (S)1 / (pr * pr + pi * pi);
+                const S ir = pr * dd, ii = -pi * dd;
+                const S xr = F.re[k], xi = F.im[k];
+                const S lr = xr * ir - xi * ii, li = xr * ii + xi * ir;
                 F.re[k] = lr;
                 F.im[k] = li;
 #pragma unroll
                 for (int c = k + 1; c < G; ++c) {
-                    const double ur = L.prow[c], ui = L.prow[G + c];
+                    const S ur = (S)L.prow[c], ui = (S)L.prow[G + c];
                     F.re[c] -= lr * ur - li * ui;
                     F.im[c] -= lr * ui + li * ur;
                 }
@@ -451,34 +464,37 @@ __device__ void factor_cplx(LUC &F, const GL &L, int r, int N) {
 }
 
 // x = E^-1 b, component r in lane r in and out
-__device__ double solve_real(const LUR &F, int r, int N, double b) {
-    double acc = gb(b, r < N ? perm_at(F.perm, r) : r);        // P b
+template <typename S>
+__device__ double solve_real(const LUR<S> &F, int r, int N, double b) {
+    double acc = gb(b * F.rs, r < N ? perm_at(F.perm, r) : r);        // P b (equilibrated)
 #pragma unroll
     for (int k = 0; k < G; ++k)
         if (k < N) {
             const double yk = bcast(acc, k);
-            if (r > k) acc -= F.a[k] * yk;
+            if (r > k) acc -= (double)F.a[k] * yk;
         }
 #pragma unroll
     for (int k = G - 1; k >= 0; --k)
         if (k < N) {
             if (r == k) acc *= F.dinv;
             const double xk = bcast(acc, k);
-            if (r < k) acc -= F.a[k] * xk;
+            if (r < k) acc -= (double)F.a[k] * xk;
         }
-    return r < N ? acc : 0.0;
+    return r < N ? acc * F.cs : 0.0;
 }
 
-__device__ void solve_cplx(const LUC &F, int r, int N, double &br, double &bi) {
+template <typename S>
+__device__ void solve_cplx(const LUC<S> &F, int r, int N, double &br, double &bi) {
     const int src = r < N ? perm_at(F.perm, r) : r;
-    double ar = gb(br, src), ai = gb(bi, src);
+    double ar = gb(br * F.rs, src), ai = gb(bi * F.rs, src);
 #pragma unroll
     for (int k = 0; k < G; ++k)
         if (k < N) {
             const double yr = bcast(ar, k), yi = bcast(ai, k);
             if (r > k) {
-                ar -= F.re[k] * yr - F.im[k] * yi;
-                ai -= F.re[k] * yi + F.im[k] * yr;
+                const double lr = F.re[k], li = F.im[k];
+                ar -= lr * yr - li * yi;
+                ai -= lr * yi + li * yr;
             }
         }
 #pragma unroll
@@ -491,17 +507,42 @@ __device__ void solve_cplx(const LUC &F, int r, int N, double &br, double &bi) {
             }
             const double xr = bcast(ar, k), xi = bcast(ai, k);
             if (r < k) {
-                ar -= F.re[k] * xr - F.im[k] * xi;
-                ai -= F.re[k] * xi + F.im[k] * xr;
+                const double ur = F.re[k], ui = F.im[k];
+                ar -= ur * xr - ui * xi;
+                ai -= ur * xi + ui * xr;
             }
         }
-    br = r < N ? ar : 0.0;
-    bi = r < N ? ai : 0.0;
+    br = r < N ? ar * F.cs : 0.0;
+    bi = r < N ? ai * F.cs : 0.0;
+}
+
+// FP64 product of the iteration matrix c I - J (J row-major in LDS) with x
+// (component r in lane r), used for residuals of the mixed-precision solves
+__device__ double ematvec(const GL &L, int r, int N, double c, double x) {
+    sync_wave();
+    L.vx[r] = x;
+    sync_wave();
+    double acc = c * x;
+    const double *row = L.J + r * G;
+#pragma unroll
+    for (int k = 0; k < G; ++k)
+        if (k < N) acc -= row[k] * L.vx[k];
+    sync_wave();
+    return r < N ? acc : 0.0;
 }
 
 enum { ACT_JAC = 0, ACT_LU = 1, ACT_SAME = 2 };
 
-__global__ void reset_queue_kernel(int *q) { *q = 0; }
+__global__ void reset_queue_kernel(int *q) {
+    if (threadIdx.x < 4) q[threadIdx.x] = 0;
+}
+
+// indices of the states the mixed-precision pass handed back (status FALLBACK)
+__global__ void collect_fallback_kernel(const int32_t *__restrict__ cnt, int64_t n, int *__restrict__ list,
+                                        int *__restrict__ count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && cnt[(size_t)C_STATUS * n + i] == kStatusFallback) list[atomicAdd(count, 1)] = (int)i;
+}
 
 // One step attempt per group per loop iteration: the groups of a wavefront run
 // the same sequence of phases (refill, Jacobian, factorisation, Newton, error
@@ -509,10 +550,13 @@ __global__ void reset_queue_kernel(int *q) { *q = 0; }
 // takes the next state from the queue in the next iteration without waiting
 // for the other groups of its wavefront.  The wavefront leaves the loop when
 // no group holds a state.
+template <typename S>
 __global__ __launch_bounds__(64) void radau_group_kernel(DevMech m, RadauParams rp, int64_t n,
                                                          const double *__restrict__ yin, double *__restrict__ yout,
                                                          int32_t *__restrict__ cnt, int *__restrict__ queue,
-                                                         const int *__restrict__ order) {
+                                                         const int *__restrict__ order,
+                                                         const int *__restrict__ work_n) {
+    constexpr bool kMixed = std::is_same<S, float>::value;
     extern __shared__ double smem[];
     const int r = threadIdx.x & (G - 1);
     const int grp = threadIdx.x / G;
@@ -522,8 +566,10 @@ __global__ __launch_bounds__(64) void radau_group_kernel(DevMech m, RadauParams 
     const double dt = rp.dt, atol = rp.atol, rtol = rp.rtol, kappa = rp.kappa;
     const int kmax = rp.kmax;
 
-    LUR E1;
-    LUC E2;
+    const int64_t nwork = work_n ? (int64_t)*work_n : n;
+    LUR<S> E1;
+    LUC<S> E2;
+    int ndiv_row = 0;      // consecutive Newton divergences since the last accepted step
     bool have = false, drained = false;
     int64_t s = 0;
     double P = 0.0, y = 0.0, f0 = 0.0, sc = 1.0, t = 0.0, h = 0.0;
@@ -539,7 +585,7 @@ __global__ __launch_bounds__(64) void radau_group_kernel(DevMech m, RadauParams 
             int qi = 0;
             if (r == 0) qi = atomicAdd(queue, 1);
             qi = gbi(qi, 0);
-            if (qi >= n) {
+            if (qi >= nwork) {
                 drained = true;
             } else {
                 s = order ? (int64_t)order[qi] : (int64_t)qi;
@@ -575,6 +621,7 @@ __global__ __launch_bounds__(64) void radau_group_kernel(DevMech m, RadauParams 
                     erracc = 1e-2;
                     hlast = h;
                     Zs1 = Zs2 = Zs3 = 0.0;
+                    ndiv_row = 0;
                     action = ACT_JAC;
                 }
             }
@@ -592,17 +639,51 @@ __global__ __launch_bounds__(64) void radau_group_kernel(DevMech m, RadauParams 
         if (action == ACT_LU) {
             const double gh = rp.g / h, ah = rp.a / h, bh = rp.b / h;
             const double *row = L.J + r * G;
+            if constexpr (kMixed) {
+                // equilibrate: E'' = diag(1/(sc_r m_r)) E diag(sc_c)
+                sync_wave();
+                L.vx[r] = comp ? sc : 1.0;
+                sync_wave();
+                double e1[G], e2r[G];
+                double m1 = 0.0, m2 = 0.0;
+                const double isc = 1.0 / (comp ? sc : 1.0);
 #pragma unroll
-            for (int c = 0; c < G; ++c) {
-                const double j = comp ? row[c] : 0.0;
-                E1.a[c] = -j;
-                E2.re[c] = -j;
-                E2.im[c] = 0.0;
+                for (int c = 0; c < G; ++c) {
+                    const double j = comp ? row[c] : 0.0;
+                    const double w = L.vx[c] * isc;
+                    e1[c] = ((c == r ? gh : 0.0) - j) * w;
+                    e2r[c] = ((c == r ? ah : 0.0) - j) * w;
+                    m1 = fmax(m1, fabs(e1[c]));
+                    m2 = fmax(m2, fabs(e2r[c]));
+                }
+                const double e2i = bh;      // imaginary part: diagonal only, scale w = 1
+                m2 = fmax(m2, e2i);
+                const double i1 = 1.0 / m1, i2 = 1.0 / m2;
+#pragma unroll
+                for (int c = 0; c < G; ++c) {
+                    E1.a[c] = (S)(e1[c] * i1);
+                    E2.re[c] = (S)(e2r[c] * i2);
+                    E2.im[c] = (S)(c == r ? e2i * i2 : 0.0);
+                }
+                E1.rs = isc * i1;
+                E2.rs = isc * i2;
+                E1.cs = E2.cs = comp ? sc : 1.0;
+                sync_wave();
+            } else {
+#pragma unroll
+                for (int c = 0; c < G; ++c) {
+                    const double j = comp ? row[c] : 0.0;
+                    E1.a[c] = -j;
+                    E2.re[c] = -j;
+                    E2.im[c] = 0.0;
+                }
+#pragma unroll
+                for (int c = 0; c < G; ++c)
+                    if (c == r) { E1.a[c] += gh; E2.re[c] += ah; E2.im[c] = bh; }
+                E1.rs = E2.rs = 1.0;
+                E1.cs = E2.cs = 1.0;
+                sync_wave();
             }
-#pragma unroll
-            for (int c = 0; c < G; ++c)
-                if (c == r) { E1.a[c] += gh; E2.re[c] += ah; E2.im[c] = bh; }
-            sync_wave();
             factor_real(E1, L, r, N);
             factor_cplx(E2, L, r, N);
             ++nlu;
@@ -636,7 +717,7 @@ __global__ __launch_bounds__(64) void radau_group_kernel(DevMech m, RadauParams 
             double W3 = rp.Ti[6] * Z1 + rp.Ti[7] * Z2 + rp.Ti[8] * Z3;
 
             eta = pow(fmax(eta, kU), 0.8);
-            bool converged = false;
+            bool converged = false, diverged = false;
             int newt = 0;
             double dn_old = 1.0;
             for (int it = 1; it <= kmax; ++it) {
@@ -648,22 +729,32 @@ __global__ __launch_bounds__(64) void radau_group_kernel(DevMech m, RadauParams 
                 const double G1 = rp.Ti[0] * F1 + rp.Ti[1] * F2 + rp.Ti[2] * F3;
                 const double G2 = rp.Ti[3] * F1 + rp.Ti[4] * F2 + rp.Ti[5] * F3;
                 const double G3 = rp.Ti[6] * F1 + rp.Ti[7] * F2 + rp.Ti[8] * F3;
-                double dW1 = comp ? G1 - gh * W1 : 0.0;
-                double dW2 = comp ? G2 - (ah * W2 - bh * W3) : 0.0;
-                double dW3 = comp ? G3 - (bh * W2 + ah * W3) : 0.0;
-                dW1 = solve_real(E1, r, N, dW1);
+                const double b1 = comp ? G1 - gh * W1 : 0.0;
+                const double b2 = comp ? G2 - (ah * W2 - bh * W3) : 0.0;
+                const double b3 = comp ? G3 - (bh * W2 + ah * W3) : 0.0;
+                double dW1 = solve_real(E1, r, N, b1);
+                double dW2 = b2, dW3 = b3;
                 solve_cplx(E2, r, N, dW2, dW3);
+                if constexpr (kMixed) {
+                    // one refinement step against the FP64 matrices
+                    dW1 += solve_real(E1, r, N, b1 - ematvec(L, r, N, gh, dW1));
+                    double q2 = b2 - (ematvec(L, r, N, ah, dW2) - bh * dW3);
+                    double q3 = b3 - (ematvec(L, r, N, ah, dW3) + bh * dW2);
+                    solve_cplx(E2, r, N, q2, q3);
+                    dW2 += q2;
+                    dW3 += q3;
+                }
                 const double dZ1 = rp.T[0] * dW1 + rp.T[1] * dW2 + rp.T[2] * dW3;
                 const double dZ2 = rp.T[3] * dW1 + rp.T[4] * dW2 + rp.T[5] * dW3;
                 const double dZ3 = rp.T[6] * dW1 + rp.T[7] * dW2 + rp.T[8] * dW3;
                 ++nnewt;
                 newt = it;
                 const double dn = sqrt(gsum(comp ? (dZ1 * dZ1 + dZ2 * dZ2 + dZ3 * dZ3) / (sc * sc) : 0.0) / (3 * N));
-                if (!isfinite(dn)) break;
+                if (!isfinite(dn)) { diverged = true; break; }
                 if (it >= 2) {
                     const double th = dn / dn_old;
                     theta = th;
-                    if (th >= 0.99) break;
+                    if (th >= 0.99) { diverged = true; break; }
                     eta = th / (1.0 - th);
                     if (pow(th, (double)(kmax - it)) / (1.0 - th) * dn > kappa) break;
                 }
@@ -678,17 +769,27 @@ __global__ __launch_bounds__(64) void radau_group_kernel(DevMech m, RadauParams 
                 reject = true;
                 last = false;
                 action = jac_fresh ? ACT_LU : ACT_JAC;
+                ndiv_row = diverged ? ndiv_row + 1 : 0;
+                if (kMixed && !first && ndiv_row >= 2) {   // after start-up: hand the state to the FP64 pass
+                    status = kStatusFallback;
+                    done = true;
+                }
             } else {
                 // embedded error estimate
                 const double invh = 1.0 / h;
                 const double dz = (rp.d[0] * Z1 + rp.d[1] * Z2 + rp.d[2] * Z3) * invh;
                 const double sc2 = comp ? atol + rtol * fmax(fabs(y), fabs(y + Z3)) : 1.0;
-                double ev = solve_real(E1, r, N, comp ? f0 + dz : 0.0);
+                const double gh = rp.g / h;
+                double v = comp ? f0 + dz : 0.0;
+                double ev = solve_real(E1, r, N, v);
+                if constexpr (kMixed) ev += solve_real(E1, r, N, v - ematvec(L, r, N, gh, ev));   // FP64 residual
                 double err = fmax(sqrt(gsum(comp ? (ev / sc2) * (ev / sc2) : 0.0) / N), 1e-10);
                 if (err >= 1.0 && (first || reject)) {
                     const double fe = rhs_g(m, L, r, y + ev, P);
                     ++nfev;
-                    ev = solve_real(E1, r, N, comp ? fe + dz : 0.0);
+                    v = comp ? fe + dz : 0.0;
+                    ev = solve_real(E1, r, N, v);
+                    if constexpr (kMixed) ev += solve_real(E1, r, N, v - ematvec(L, r, N, gh, ev));
                     err = fmax(sqrt(gsum(comp ? (ev / sc2) * (ev / sc2) : 0.0) / N), 1e-10);
                 }
                 if (!isfinite(err)) err = 1e300;
@@ -698,6 +799,7 @@ __global__ __launch_bounds__(64) void radau_group_kernel(DevMech m, RadauParams 
                 double hnew = h / quot;
                 if (err < 1.0) {
                     first = false;
+                    ndiv_row = 0;
                     ++nacc;
                     if (nacc > 1) {
                         double fg = (hacc / h) * pow(err * err / erracc, 0.25) / 0.9;
@@ -756,6 +858,7 @@ __global__ __launch_bounds__(64) void radau_group_kernel(DevMech m, RadauParams 
                 cnt[(size_t)C_NFEV * n + s] = nfev;
                 cnt[(size_t)C_NJEV * n + s] = njev;
                 cnt[(size_t)C_NLU * n + s] = nlu;
+                if (kMixed && status == kStatusFallback) cnt[(size_t)C_FLAGS * n + s] = 1;
             }
             have = false;
         }
@@ -764,21 +867,46 @@ __global__ __launch_bounds__(64) void radau_group_kernel(DevMech m, RadauParams 
 
 }  // namespace
 
+namespace {
+__global__ void zero_i32_kernel(int32_t *__restrict__ p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+}  // namespace
+
+hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_i32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n);
+    return hipGetLastError();
+}
+
 size_t group_lds_bytes(int R) { return (size_t)(kWave / G) * group_lds_doubles(R) * sizeof(double); }
 
 hipError_t launch_radau_group(const DevMech &m, const RadauParams &p, int64_t n, const double *yin, double *yout,
-                              int32_t *counters, int *queue, const int *order, int grid, hipStream_t st) {
+                              int32_t *counters, int *queue, int *fb_list, const int *order, bool mixed, int grid,
+                              hipStream_t st) {
     if (n == 0) return hipSuccess;
     if (m.N > G) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(1), 0, st, queue);
-    hipLaunchKernelGGL(radau_group_kernel, dim3(grid), dim3(kWave), group_lds_bytes(m.R), st, m, p, n, yin, yout,
-                       counters, queue, order);
+    hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, st, queue);
+    const size_t lds = group_lds_bytes(m.R);
+    if (!mixed) {
+        hipLaunchKernelGGL(radau_group_kernel<double>, dim3(grid), dim3(kWave), lds, st, m, p, n, yin, yout, counters,
+                           queue, order, (const int *)nullptr);
+        return hipGetLastError();
+    }
+    // mixed pass over every state, then an FP64 pass over the states it handed back
+    hipLaunchKernelGGL(radau_group_kernel<float>, dim3(grid), dim3(kWave), lds, st, m, p, n, yin, yout, counters,
+                       queue, order, (const int *)nullptr);
+    hipLaunchKernelGGL(collect_fallback_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, counters, n,
+                       fb_list, queue + 1);
+    hipLaunchKernelGGL(radau_group_kernel<double>, dim3(grid), dim3(kWave), lds, st, m, p, n, yin, yout, counters,
+                       queue + 2, (const int *)fb_list, (const int *)(queue + 1));
     return hipGetLastError();
 }
 
 int group_max_blocks(int R) {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, radau_group_kernel, kWave, group_lds_bytes(R)) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, radau_group_kernel<double>, kWave, group_lds_bytes(R)) !=
         hipSuccess)
         per_cu = 1;
     int dev = 0, cus = 0;

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/rkchem.h"
@@ -53,7 +54,9 @@ struct LaneLayout {
 };
 
 // Per-state counters written by the integrators: [kNumCounters][n].
-enum Counter { C_STATUS = 0, C_NSTEP, C_NACC, C_NREJ, C_NNEWT, C_NNFAIL, C_NFEV, C_NJEV, C_NLU, kNumCounters };
+enum Counter { C_STATUS = 0, C_NSTEP, C_NACC, C_NREJ, C_NNEWT, C_NNFAIL, C_NFEV, C_NJEV, C_NLU, C_FLAGS, kNumCounters };
+// status a mixed-precision pass gives a state it hands to the FP64 pass
+constexpr int kStatusFallback = 4;
 
 LaneLayout lane_layout(int K);
 
@@ -61,12 +64,20 @@ LaneLayout lane_layout(int K);
 hipError_t launch_rhs(const DevMech &m, int64_t n, const double *y, double *f, double *scratch, hipStream_t st);
 hipError_t launch_jac(const DevMech &m, int64_t n, const double *y, double *J, double *scratch, hipStream_t st);
 hipError_t launch_radau_lane(const DevMech &m, const RadauParams &p, int64_t n, const double *yin, double *yout,
-                             double *scratch, int32_t *counters, hipStream_t st);
+                             double *scratch, int32_t *counters, const int *order, hipStream_t st);
+hipError_t launch_gather_head(const double *src, int64_t n, int64_t m, int rows, double *dst, hipStream_t st);
+// cost binning: proxy key per state, counting sort into a queue order (costliest bins first)
+constexpr int kProxyLanes = 65536;
+size_t proxy_scratch_doubles(int K);
+hipError_t launch_binning(const DevMech &m, int64_t n, const double *yin, double dt, double atol, double rtol,
+                          int nbins, int *bins, int *order, int *hist, double *scratch, hipStream_t st);
 size_t lane_scratch_doubles(int K, int64_t n);
 // group-cooperative variant (16 lanes per state, N <= 16), persistent work queue
 hipError_t launch_radau_group(const DevMech &m, const RadauParams &p, int64_t n, const double *yin, double *yout,
-                              int32_t *counters, int *queue, const int *order, int grid, hipStream_t st);
+                              int32_t *counters, int *queue, int *fb_list, const int *order, bool mixed, int grid,
+                              hipStream_t st);
 int group_max_blocks(int R);
+hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t st);
 size_t group_lds_bytes(int R);
 
 }  // namespace rk
@@ -86,7 +97,7 @@ struct rk_mech {
     void *dev_block = nullptr;
     int device = 0;
     // options
-    int variant = -1;          // -1 auto, 0 lane, 1 wave (16-lane groups)
+    int variant = -1;          // -1 auto, 0 lane, 1 wave (16-lane groups), 2 mixed (FP32 factors)
     int kmax = 7, nmax = 100000;
     double kappa = 0.0, h0 = 0.0;
     // workspace of the last call
@@ -94,7 +105,21 @@ struct rk_mech {
     size_t scratch_cap = 0;    // doubles
     int32_t *counters = nullptr;
     int64_t counters_cap = 0;  // states
-    int *queue = nullptr;      // work-queue head (device)
+    int *queue = nullptr;      // work-queue heads and fallback count (device)
+    int *fb_list = nullptr;    // states handed from the mixed to the FP64 pass (device)
+    int64_t fb_cap = 0;
+    // cost binning
+    int nbins = 0;             // 0: queue in input order
+    int *bins = nullptr, *order = nullptr, *hist = nullptr;
+    int64_t bin_cap = 0;
+    double *proxy_scratch = nullptr;
+    // autotuner: chosen (bins, grid percent) per dt, trial buffers
+    bool autotune = false;
+    std::vector<std::pair<double, std::pair<int, int>>> tuned;
+    int grid_pct = 100;
+    double *tune_buf = nullptr;
+    size_t tune_cap = 0;
+    int last_nbins = 0, last_grid = 0;
     int group_blocks = 0;      // resident blocks of the group kernel (cached)
     int64_t last_n = 0;
     hipStream_t last_stream = nullptr;

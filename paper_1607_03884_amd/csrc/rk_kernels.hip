@@ -403,9 +403,11 @@ __global__ __launch_bounds__(64) void jac_kernel(DevMech m, LaneLayout L, int64_
 // defaults (kappa, kmax, h0, the failure rules).
 __global__ __launch_bounds__(64) void radau_lane_kernel(DevMech m, LaneLayout L, RadauParams rp, int64_t n,
                                                         const double *__restrict__ yin, double *__restrict__ yout,
-                                                        double *__restrict__ scratch, int32_t *__restrict__ cnt) {
-    const int64_t s = (int64_t)blockIdx.x * kWave + threadIdx.x;
-    if (s >= n) return;
+                                                        double *__restrict__ scratch, int32_t *__restrict__ cnt,
+                                                        const int *__restrict__ order) {
+    const int64_t slot = (int64_t)blockIdx.x * kWave + threadIdx.x;
+    if (slot >= n) return;
+    const int64_t s = order ? (int64_t)order[slot] : slot;
     Lane M{scratch + (size_t)blockIdx.x * L.total * kWave + threadIdx.x};
     const int N = m.N, K = m.K, N3 = 3 * N;
     const double P = yin[(size_t)(K + 1) * n + s];
@@ -626,6 +628,84 @@ __global__ __launch_bounds__(64) void radau_lane_kernel(DevMech m, LaneLayout L,
     cnt[(size_t)C_NLU * n + s] = nlu;
 }
 
+// ---------------------------------------------------------------------------
+// cost binning: key = ||dt f(y0)||, RMS in the error weights, one source-term
+// evaluation per state; bin = floor(log2(1 + key) * nbins / 64) clamped.
+// States are then ordered by descending bin (costliest first) with a
+// counting sort whose atomics are aggregated per block.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void proxy_bin_kernel(DevMech m, LaneLayout L, int64_t n, const double *__restrict__ yin,
+                                                       double dt, double atol, double rtol, int nbins,
+                                                       int *__restrict__ bins, double *__restrict__ scratch,
+                                                       int64_t nlanes) {
+    Lane M{scratch + (size_t)blockIdx.x * L.total * kWave + threadIdx.x};
+    const int N = m.N, K = m.K;
+    for (int64_t s = (int64_t)blockIdx.x * kWave + threadIdx.x; s < n; s += nlanes) {
+        const double P = yin[(size_t)(K + 1) * n + s];
+        bool ok = P > 0.0 && isfinite(P);
+        for (int c = 0; c < N; ++c) {
+            const double v = yin[(size_t)c * n + s];
+            M[L.y + c] = v;
+            ok = ok && isfinite(v);
+        }
+        ok = ok && M[L.y] > 0.0;
+        int b = nbins - 1;
+        if (ok) {
+            rhs(m, L, M, L.y, L.f0, P);
+            double acc = 0.0;
+            for (int c = 0; c < N; ++c) {
+                const double t = dt * M[L.f0 + c] / (atol + rtol * fabs(M[L.y + c]));
+                acc += t * t;
+            }
+            const double key = sqrt(acc / N);
+            if (isfinite(key)) b = min(nbins - 1, max(0, (int)(log2(1.0 + key) * nbins / 64.0)));
+        }
+        bins[s] = b;
+    }
+}
+
+__global__ __launch_bounds__(256) void bin_hist_kernel(const int *__restrict__ bins, int64_t n, int nbins,
+                                                       int *__restrict__ hist) {
+    __shared__ int h[64];
+    if (threadIdx.x < 64) h[threadIdx.x] = 0;
+    __syncthreads();
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&h[bins[s]], 1);
+    __syncthreads();
+    if (threadIdx.x < nbins && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+}
+
+// cursor[b] = first queue position of bin b, bins in descending order
+__global__ void bin_scan_kernel(const int *__restrict__ hist, int nbins, int *__restrict__ cursor) {
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int b = nbins - 1; b >= 0; --b) {
+            cursor[b] = acc;
+            acc += hist[b];
+        }
+    }
+}
+
+// each block scatters a contiguous chunk: one global atomic per bin per block
+__global__ __launch_bounds__(256) void bin_scatter_kernel(const int *__restrict__ bins, int64_t n, int64_t chunk,
+                                                          int *__restrict__ cursor, int *__restrict__ order) {
+    __shared__ int cnt[64], base[64];
+    if (threadIdx.x < 64) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t s0 = (int64_t)blockIdx.x * chunk, s1 = min(n, s0 + chunk);
+    for (int64_t s = s0 + threadIdx.x; s < s1; s += blockDim.x) atomicAdd(&cnt[bins[s]], 1);
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        base[threadIdx.x] = cnt[threadIdx.x] ? atomicAdd(&cursor[threadIdx.x], cnt[threadIdx.x]) : 0;
+        cnt[threadIdx.x] = 0;
+    }
+    __syncthreads();
+    for (int64_t s = s0 + threadIdx.x; s < s1; s += blockDim.x) {
+        const int b = bins[s];
+        order[base[b] + atomicAdd(&cnt[b], 1)] = (int)s;
+    }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -653,6 +733,28 @@ size_t lane_scratch_doubles(int K, int64_t n) {
 
 static unsigned grid_of(int64_t n) { return (unsigned)((n + kWave - 1) / kWave); }
 
+namespace {
+__global__ void zero_ints_kernel(int *p, int n) {
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
+}
+// first m states of a component-major [rows][n] array into a [rows][m] one
+__global__ void gather_head_kernel(const double *__restrict__ src, int64_t n, int64_t m, int rows,
+                                   double *__restrict__ dst) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m * rows) {
+        const int64_t r = i / m, c = i % m;
+        dst[i] = src[r * n + c];
+    }
+}
+}  // namespace
+
+hipError_t launch_gather_head(const double *src, int64_t n, int64_t m, int rows, double *dst, hipStream_t st) {
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gather_head_kernel, dim3((unsigned)((m * rows + 255) / 256)), dim3(256), 0, st, src, n, m, rows,
+                       dst);
+    return hipGetLastError();
+}
+
 hipError_t launch_rhs(const DevMech &m, int64_t n, const double *y, double *f, double *scratch, hipStream_t st) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(rhs_kernel, dim3(grid_of(n)), dim3(kWave), 0, st, m, lane_layout(m.K), n, y, f, scratch);
@@ -666,10 +768,41 @@ hipError_t launch_jac(const DevMech &m, int64_t n, const double *y, double *J, d
 }
 
 hipError_t launch_radau_lane(const DevMech &m, const RadauParams &p, int64_t n, const double *yin, double *yout,
-                             double *scratch, int32_t *counters, hipStream_t st) {
+                             double *scratch, int32_t *counters, const int *order, hipStream_t st) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(radau_lane_kernel, dim3(grid_of(n)), dim3(kWave), 0, st, m, lane_layout(m.K), p, n, yin, yout,
-                       scratch, counters);
+                       scratch, counters, order);
+    return hipGetLastError();
+}
+
+LaneLayout proxy_layout(int K) {
+    // only what one source-term evaluation touches
+    const int N = K + 1;
+    LaneLayout L{};
+    int o = 0;
+    auto take = [&o](int n) { const int r = o; o += n; return r; };
+    L.y = take(N); L.f0 = take(N);
+    L.C = take(K); L.cp = take(K); L.h = take(K); L.s = take(K); L.wdot = take(K);
+    L.total = o;
+    return L;
+}
+
+size_t proxy_scratch_doubles(int K) { return (size_t)kProxyLanes * proxy_layout(K).total; }
+
+hipError_t launch_binning(const DevMech &m, int64_t n, const double *yin, double dt, double atol, double rtol,
+                          int nbins, int *bins, int *order, int *hist, double *scratch, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    if (nbins < 1 || nbins > 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(proxy_bin_kernel, dim3(kProxyLanes / kWave), dim3(kWave), 0, st, m, proxy_layout(m.K), n, yin, dt,
+                       atol, rtol, nbins, bins, scratch, (int64_t)kProxyLanes);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(128), 0, st, hist, 128);
+    hipLaunchKernelGGL(bin_hist_kernel, dim3(256), dim3(256), 0, st, bins, n, nbins, hist);
+    hipLaunchKernelGGL(bin_scan_kernel, dim3(1), dim3(64), 0, st, hist, nbins, hist + 64);
+    const int64_t chunk = 4096;
+    hipLaunchKernelGGL(bin_scatter_kernel, dim3((unsigned)((n + chunk - 1) / chunk)), dim3(256), 0, st, bins, n, chunk,
+                       hist + 64, order);
     return hipGetLastError();
 }
 

@@ -88,7 +88,7 @@ def _run(torch_dev, g, rows, dt, **opts):
     return out.cpu().numpy().T, st
 
 
-VARIANTS = ["lane", "wave"]
+VARIANTS = ["lane", "wave", "mixed"]
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
@@ -101,9 +101,10 @@ def test_cfg0_full_parity(torch_dev, gm13, m13, variant):
     eT, eY = integration_errors(got, ref, 13)
     same = np.mean(st["per_state_steps"] == res["nstep"])
     print(f"cfg0: max rel err T {eT:.2e} Y {eY:.2e}, identical step counts {same:.4f}, "
-          f"kernel {st['kernel_ms']:.1f} ms")
+          f"kernel {st['kernel_ms']:.1f} ms, fp32 fallbacks {st['fp32_fallback']}")
     assert eT <= TOL and eY <= TOL
-    assert same >= 0.99
+    # the FP64 paths take the oracle's decisions; FP32 factors change the iteration path
+    assert same >= (0.99 if variant != "mixed" else 0.5)
     assert np.array_equal(got[:, -1], rows[:, -1])
     gm13.set_option("variant", "lane")
 
@@ -190,7 +191,9 @@ def test_cfg1_full_size_sampled(torch_dev, gm13, m13, dt, variant):
               f"{st['per_state_steps'][badi[:8]]}, oracle status {res['status']} steps {res['nstep']}")
     assert np.all(status == 0)
     assert np.all(np.isfinite(got))
-    assert np.abs(got[:, 1:14].sum(1) - rows[:, 1:14].sum(1)).max() <= 1e-12
+    # sum Y is an invariant of every Newton iterate with exact solves (rounding
+    # level); FP32 factors keep it to the Newton tolerance
+    assert np.abs(got[:, 1:14].sum(1) - rows[:, 1:14].sum(1)).max() <= (1e-12 if variant != "mixed" else 1e-9)
     steps = st["per_state_steps"]
     rng = np.random.default_rng(77)
     top = np.argsort(steps)[-256:]
@@ -198,5 +201,35 @@ def test_cfg1_full_size_sampled(torch_dev, gm13, m13, dt, variant):
     ref, res = m13.integrate(rows[pick], dt)
     eT, eY = integration_errors(got[pick], ref, 13)
     print(f"cfg1 dt={dt}: kernel {st['kernel_ms']:.1f} ms, steps {st['steps']}, max rel err T {eT:.2e} Y {eY:.2e}, "
-          f"D64 mean {st['d_mean64']:.3f}")
+          f"D64 mean {st['d_mean64']:.3f}, fp32 fallbacks {st['fp32_fallback']}")
     assert eT <= TOL and eY <= TOL
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_schedule_invariance(torch_dev, gm13, variant):
+    """Queue order (input order, 16 cost bins, autotuned bins and grid) changes
+    which lanes/groups integrate a state, never its result: per-state outputs
+    and step counts are bitwise identical.  Outputs start as NaN so a state
+    dropped or duplicated by the ordering would show."""
+    banner(f"schedule invariance variant={variant}")
+    torch, _ = torch_dev
+    rows = configs.states_for(configs.WORKLOADS["cfg1"], 40000)
+    y = _dev(torch_dev, rows)
+    outs, steps = [], []
+    for opts in ({"binning": 0}, {"binning": 16}, {"binning": 0, "autotune": 1}):
+        gm13.set_option("variant", variant)
+        for k, v in opts.items():
+            gm13.set_option(k, v)
+        out = torch.full_like(y, float("nan"))
+        gm13.integrate(y, 1e-6, y_out=out)
+        torch.cuda.synchronize()
+        st = gm13.stats(per_state=True)
+        outs.append(out.cpu().numpy())
+        steps.append(st["per_state_steps"].copy())
+        print(f"{variant} {opts}: kernel {st['kernel_ms']:.1f} ms, bins {st['nbins_used']}, grid {st['grid_used']}")
+    for k, v in (("binning", 0), ("autotune", 0), ("variant", "auto")):
+        gm13.set_option(k, v)
+    assert np.all(np.isfinite(outs[0]))
+    for o, s in zip(outs[1:], steps[1:]):
+        assert np.array_equal(o, outs[0])
+        assert np.array_equal(s, steps[0])
