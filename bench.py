@@ -51,7 +51,11 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cfg1")
-    ap.add_argument("--variant", default="wave")
+    ap.add_argument("--variant", default="wave", help="lane | wave | mixed")
+    ap.add_argument("--binning", type=int, default=0, help="cost bins of the work queue (0 = input order)")
+    ap.add_argument("--autotune", type=int, default=1, help="1: let the library tune bins and grid per dt")
+    ap.add_argument("--compare", default="lane,mixed",
+                    help="other variants timed (1 warmup + 1 step each) for the comparison fields")
     ap.add_argument("--cpu-sample", type=int, default=16384)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
@@ -81,6 +85,8 @@ def main() -> int:
     out = torch.empty_like(y)
     mech = Mechanism(path)
     mech.set_option("variant", args.variant)
+    mech.set_option("binning", args.binning)
+    mech.set_option("autotune", args.autotune)
     stream = torch.cuda.current_stream()
     print(f"[bench] {wl.name}: {n} states, mechanism {wl.mech} (K={mech.K}, R={mech.R}), dts {wl.dts}", flush=True)
 
@@ -129,6 +135,7 @@ def main() -> int:
         tot_flops += fl["flops"]
         tot_ms += kernel_ms[dt]
         per_dt[f"{dt:g}"] = {"states_per_s": n / (kernel_ms[dt] * 1e-3), "kernel_ms": kernel_ms[dt],
+                             "bins": st["nbins_used"], "grid": st["grid_used"], "fp32_fallback": st["fp32_fallback"],
                              "steps_per_state": st["steps"] / n, "max_steps": st["max_steps"],
                              "newton_per_step": st["newton_iters"] / max(st["steps"], 1),
                              "jac_evals": st["jac_evals"], "lu_factor": st["lu_factor"],
@@ -139,6 +146,27 @@ def main() -> int:
     roofline = {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": measured_traffic(kname, wl.name),
                 "kernel": kname, "flops_per_launch": tot_flops / len(wl.dts)}
+
+    # the other variants, same inputs, for the comparison fields (not the headline value)
+    compare = {}
+    for var in [v for v in args.compare.split(",") if v and v != args.variant]:
+        other = Mechanism(path)
+        other.set_option("variant", var)
+        other.set_option("autotune", args.autotune if var != "lane" else 0)
+        rate = {}
+        for dt in wl.dts:
+            other.integrate(y, dt, configs.ATOL, configs.RTOL, y_out=out, stream=stream)
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            other.integrate(y, dt, configs.ATOL, configs.RTOL, y_out=out, stream=stream)
+            b.record(stream)
+            torch.cuda.synchronize()
+            rate[f"{dt:g}"] = n / (a.elapsed_time(b) * 1e-3)
+        compare[var] = {"states_per_s": rate,
+                        "per_step_states_per_s": n * len(wl.dts) / sum(n / r for r in rate.values())}
+        other.close()
+        print(f"[bench] compared {var}: {compare[var]['per_step_states_per_s']:.0f} states/s", flush=True)
 
     cpu = None
     parity = None
@@ -172,8 +200,10 @@ def main() -> int:
         "config": {"workload": f"{wl.name}: synthetic {wl.mech} ({mech.K} species, {mech.R} reversible reactions), "
                                f"{n} PaSR-like states, one global step at each of {list(wl.dts)} s",
                    "n_states": n, "dts": list(wl.dts), "atol": configs.ATOL, "rtol": configs.RTOL,
-                   "variant": args.variant, "path": "plain FP64"},
+                   "variant": args.variant, "autotune": args.autotune, "binning": args.binning,
+                   "path": "mixed FP32 factors" if args.variant == "mixed" else "plain FP64"},
         "per_dt": per_dt,
+        "compare": compare,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "parity": parity,

@@ -40,7 +40,7 @@ extern "C" {
 /* per-state status codes */
 #define RK_ST_OK 0           /* reached t = dt */
 #define RK_ST_STEP_LIMIT 1   /* more step attempts than the limit (option nmax) */
-#define RK_ST_H_UNDERFLOW 2  /* step size fell below 1e-14 dt */
+#define RK_ST_H_UNDERFLOW 2  /* step size too small to advance t (0.1 h <= u t) */
 #define RK_ST_NONFINITE 3    /* input state not finite, T <= 0 or P <= 0; y_out = y_in */
 
 typedef struct rk_mech rk_mech;
@@ -144,6 +144,35 @@ int rk_dbg_rhs(rk_mech *mech, int64_t n, const double *d_y, double *d_f, void *s
 /* rk_dbg_jacobian — analytical Jacobian for n states: d_J receives
  * (K+1)^2 * n doubles, element (r, c) of state i at (r*(K+1) + c)*n + i. */
 int rk_dbg_jacobian(rk_mech *mech, int64_t n, const double *d_y, double *d_J, void *stream);
+
+/* ---- learned stage/step predictor network --------------------------------
+ * A multilayer perceptron with widths dims[0] -> ... -> dims[n-1], GELU
+ * (x Phi(x), erf form) on hidden layers, linear output.  Parameters are FP32
+ * masters used as BF16 (round-to-nearest-even) in every product, with FP32
+ * accumulation.  Flat parameter order: per layer W [d_out][d_in] row-major,
+ * then b [d_out].  Device arrays (d_*) are row-major [B][width] float32.
+ * Loss: sum_b mask_b sum_o w_o (y_bo - t_bo)^2 * inv_count. */
+typedef struct rk_mlp rk_mlp;
+
+/* rk_mlp_create — allocate a network on the current device (2..8 widths,
+ * each 1..4096); parameters start at zero.  RK_EINVAL / RK_ENOMEM. */
+int rk_mlp_create(int32_t n_dims, const int32_t *dims, rk_mlp **out);
+void rk_mlp_free(rk_mlp *mlp);
+int64_t rk_mlp_param_count(const rk_mlp *mlp);
+/* host float32 arrays of rk_mlp_param_count entries; set also resets Adam */
+int rk_mlp_set_params(rk_mlp *mlp, const float *host_params, int64_t count);
+int rk_mlp_get_params(const rk_mlp *mlp, float *host_params, int64_t count);
+/* d_y[B][dims[n-1]] = network(d_x[B][dims[0]]) */
+int rk_mlp_forward(rk_mlp *mlp, int64_t batch, const float *d_x, float *d_y, void *stream);
+/* loss (d_loss, one float) and its gradient (d_grad, param_count floats, may
+ * be NULL) at the current parameters; inv_count = 1 / sum(mask); no update.
+ * Synchronises the stream (reads the mask). */
+int rk_mlp_grads(rk_mlp *mlp, int64_t batch, const float *d_x, const float *d_t, const float *d_mask,
+                 const float *d_wout, float *d_grad, float *d_loss, void *stream);
+/* one Adam step (beta 0.9, 0.999, eps 1e-8, learning rate lr) on the loss */
+int rk_mlp_train_step(rk_mlp *mlp, int64_t batch, const float *d_x, const float *d_t, const float *d_mask,
+                      const float *d_wout, float inv_count, float lr, float *d_loss, void *stream);
+const char *rk_mlp_last_error(void);
 
 #ifdef __cplusplus
 }

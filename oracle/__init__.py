@@ -77,6 +77,7 @@ def lib():
         L.or_integrate_batch.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, dp, dp,
                                          ctypes.c_double, ctypes.c_double, ctypes.POINTER(Opts), dp,
                                          ctypes.c_void_p, ctypes.c_int]
+        L.or_integrate_batch2.argtypes = L.or_integrate_batch.argtypes + [dp]
         L.or_integrate_linear.argtypes = [ctypes.c_int, dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                           ctypes.POINTER(Opts), dp, ctypes.POINTER(Result), dp, ctypes.c_int]
         L.or_fixed_steps.argtypes = [ctypes.c_void_p, dp, ctypes.c_double, ctypes.c_int, dp]
@@ -169,6 +170,20 @@ class Mech:
         lib().or_integrate_batch(self.h, n, dt, _p(st), _p(out), atol, rtol, ctypes.byref(o), h0p,
                                  res.ctypes.data_as(ctypes.c_void_p), nthreads)
         return out, res
+
+    def integrate_first_step(self, states: np.ndarray, dt: float, atol: float = 1e-10, rtol: float = 1e-6,
+                             nthreads: int = 0):
+        """As integrate, also returning the first accepted step's stage
+        increments Z [n, 3, N] (zeros for states that never accepted a step)."""
+        st = np.ascontiguousarray(states, dtype=np.float64)
+        n = st.shape[0]
+        out = np.zeros_like(st)
+        res = np.zeros(n, dtype=RESULT_DTYPE)
+        z = np.zeros((n, 3, self.N))
+        o = default_opts()
+        lib().or_integrate_batch2(self.h, n, dt, _p(st), _p(out), atol, rtol, ctypes.byref(o), None,
+                                  res.ctypes.data_as(ctypes.c_void_p), nthreads, _p(z))
+        return out, res, z
 
     def fixed_steps(self, state: np.ndarray, dt: float, nsteps: int) -> np.ndarray:
         st = np.ascontiguousarray(state, dtype=np.float64)

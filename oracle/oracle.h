@@ -103,6 +103,12 @@ int or_integrate_batch(const or_mech *m, int64_t n, double dt, const double *y_i
                        double atol, double rtol, const or_opts *o, const double *h0,
                        or_result *res, int nthreads);
 
+/* as or_integrate_batch, also returning the stage increments Z = (z1, z2, z3)
+ * of each state's first accepted step in zfirst[n][3N] (may be NULL) */
+int or_integrate_batch2(const or_mech *m, int64_t n, double dt, const double *y_in, double *y_out,
+                        double atol, double rtol, const or_opts *o, const double *h0,
+                        or_result *res, int nthreads, double *zfirst);
+
 /* Radau IIA on the linear system y' = M y (row-major N x N), for the
  * closed-form checks.  Accepted step sizes are written to hrec (capacity cap). */
 int or_integrate_linear(int N, const double *M, const double *y0, double dt, double atol, double rtol,

@@ -183,7 +183,7 @@ static int finite_vec(const double *v, int n) {
 
 /* Integrate y over [0, dt] in place. */
 static int radau_core(const problem *pb, double dt, double *y, double atol, double rtol, const or_opts *o,
-                      double h0, or_result *res, double *hrec, int cap) {
+                      double h0, or_result *res, double *hrec, int cap, double *zfirst) {
     const int N = pb->N, N3 = 3 * N;
     rconst k;
     radau_consts(&k);
@@ -193,7 +193,6 @@ static int radau_core(const problem *pb, double dt, double *y, double atol, doub
     /* (reading) Newton stopping constant: max(10 u / rtol, min(0.03, sqrt(rtol))) */
     const double kappa = o->kappa > 0 ? o->kappa : fmax(10.0 * UROUND / rtol, fmin(0.03, sqrt(rtol)));
     const double safe = 0.9, facl = 5.0, facr = 0.125, thet = 1e-3;
-    const double hmin = 1e-14 * dt;
 
     size_t nd = (size_t)N * N;
     double *J = malloc(sizeof(double) * nd);
@@ -238,7 +237,8 @@ static int radau_core(const problem *pb, double dt, double *y, double atol, doub
         }
         action = SAME;
         if (res->nstep >= nmax) { res->status = OR_STEP_LIMIT; break; }
-        if (h < hmin) { res->status = OR_H_UNDERFLOW; break; }
+        /* (reading) step too small: it no longer advances t (Hairer-Wanner code criterion) */
+        if (0.1 * h <= UROUND * t || h < 1e-300) { res->status = OR_H_UNDERFLOW; break; }
         res->nstep++;
 
         /* starting values: zero on the first step, otherwise the previous
@@ -362,7 +362,10 @@ static int radau_core(const problem *pb, double dt, double *y, double atol, doub
             }
             hacc = h;
             erracc = fmax(1e-2, err);
-            if (res->naccept == 1) res->h_first = h;
+            if (res->naccept == 1) {
+                res->h_first = h;
+                if (zfirst) memcpy(zfirst, Z, sizeof(double) * N3);
+            }
             if (hrec && res->naccept <= cap) hrec[res->naccept - 1] = h;
             memcpy(Zs, Z, sizeof(double) * N3);
             hlast = h;
@@ -412,9 +415,9 @@ static void chem_j(void *c, const double *y, double *J) {
     if (x->iso) or_jac_iso(x->m, y, x->P, J); else or_jac(x->m, y, x->P, J);
 }
 
-int or_integrate_batch(const or_mech *m, int64_t n, double dt, const double *y_in, double *y_out,
-                       double atol, double rtol, const or_opts *o, const double *h0,
-                       or_result *res, int nthreads) {
+int or_integrate_batch2(const or_mech *m, int64_t n, double dt, const double *y_in, double *y_out,
+                        double atol, double rtol, const or_opts *o, const double *h0,
+                        or_result *res, int nthreads, double *zfirst) {
     const int K = m->K, N = K + 1, S = K + 2;
     or_opts dflt;
     if (!o) { or_default_opts(&dflt); o = &dflt; }
@@ -437,7 +440,8 @@ int or_integrate_batch(const or_mech *m, int64_t n, double dt, const double *y_i
             res[i].status = OR_NONFINITE;
             memcpy(out, row, sizeof(double) * S);
         } else {
-            radau_core(&pb, dt, y, atol, rtol, o, h0 ? h0[i] : 0.0, &res[i], NULL, 0);
+            radau_core(&pb, dt, y, atol, rtol, o, h0 ? h0[i] : 0.0, &res[i], NULL, 0,
+                       zfirst ? zfirst + i * 3 * N : NULL);
             memcpy(out, y, sizeof(double) * N);
             out[K + 1] = row[K + 1];
         }
@@ -464,7 +468,13 @@ int or_integrate_linear(int N, const double *M, const double *y0, double dt, dou
     lin_ctx cx = { N, M };
     problem pb = { N, lin_f, lin_j, &cx };
     memcpy(y_out, y0, sizeof(double) * N);
-    return radau_core(&pb, dt, y_out, atol, rtol, o, 0.0, res, hrec, cap);
+    return radau_core(&pb, dt, y_out, atol, rtol, o, 0.0, res, hrec, cap, NULL);
+}
+
+int or_integrate_batch(const or_mech *m, int64_t n, double dt, const double *y_in, double *y_out,
+                       double atol, double rtol, const or_opts *o, const double *h0,
+                       or_result *res, int nthreads) {
+    return or_integrate_batch2(m, n, dt, y_in, y_out, atol, rtol, o, h0, res, nthreads, NULL);
 }
 
 /* Fixed-step Radau IIA: nsteps equal steps of size dt/nsteps, the collocation

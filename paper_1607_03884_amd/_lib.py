@@ -30,7 +30,9 @@ class RkStats(ctypes.Structure):
 
 
 EXPORTS = ["mech_load", "mech_free", "mech_dims", "radau_integrate", "stats_get", "radau_set_option",
-           "rk_last_error", "rk_dbg_rhs", "rk_dbg_jacobian"]
+           "rk_last_error", "rk_dbg_rhs", "rk_dbg_jacobian",
+           "rk_mlp_create", "rk_mlp_free", "rk_mlp_param_count", "rk_mlp_set_params", "rk_mlp_get_params",
+           "rk_mlp_forward", "rk_mlp_grads", "rk_mlp_train_step", "rk_mlp_last_error"]
 
 _lib = None
 
@@ -56,6 +58,17 @@ def lib():
         L.rk_last_error.restype = ctypes.c_char_p
         L.rk_dbg_rhs.argtypes = [vp, i64, vp, vp, vp]
         L.rk_dbg_jacobian.argtypes = [vp, i64, vp, vp, vp]
+        L.rk_mlp_create.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(vp)]
+        L.rk_mlp_free.argtypes = [vp]
+        L.rk_mlp_free.restype = None
+        L.rk_mlp_param_count.argtypes = [vp]
+        L.rk_mlp_param_count.restype = i64
+        L.rk_mlp_set_params.argtypes = [vp, vp, i64]
+        L.rk_mlp_get_params.argtypes = [vp, vp, i64]
+        L.rk_mlp_forward.argtypes = [vp, i64, vp, vp, vp]
+        L.rk_mlp_grads.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp]
+        L.rk_mlp_train_step.argtypes = [vp, i64, vp, vp, vp, vp, ctypes.c_float, ctypes.c_float, vp, vp]
+        L.rk_mlp_last_error.restype = ctypes.c_char_p
         _lib = L
     return _lib
 

@@ -590,7 +590,6 @@ int radau_integrate(rk_mech *m, int64_t n, double dt, const double *yin, double 
     p.nmax = m->nmax;
     p.kappa = m->kappa > 0.0 ? m->kappa : std::max(10.0 * 2.220446049250313e-16 / rtol, std::min(0.03, std::sqrt(rtol)));
     p.h0 = m->h0 > 0.0 ? m->h0 : std::min(dt, 1e-6);
-    p.hmin = 1e-14 * dt;
     int nbins = m->nbins, gpct = m->grid_pct;
     if (m->autotune && n >= 4096) {
         int rc2 = autotune(m, n, dt, yin, atol, rtol, st, p, variant, nbins, gpct);

@@ -693,7 +693,7 @@ __global__ __launch_bounds__(64) void radau_group_kernel(DevMech m, RadauParams 
         if (nstep >= rp.nmax) {
             status = RK_ST_STEP_LIMIT;
             done = true;
-        } else if (h < rp.hmin) {
+        } else if (0.1 * h <= kU * t || h < 1e-300) {   // the step no longer advances t
             status = RK_ST_H_UNDERFLOW;
             done = true;
         } else {

@@ -36,7 +36,7 @@ struct DevMech {
 
 // Radau IIA constants and integrator parameters (computed on the host).
 struct RadauParams {
-    double dt, atol, rtol, kappa, h0, hmin;
+    double dt, atol, rtol, kappa, h0;
     int kmax, nmax;
     double g, a, b;          // eigenvalues of A^-1: g, a +- i b
     double T[9], Ti[9];      // T^-1 A^-1 T = [[g,0,0],[0,a,-b],[0,b,a]] (row-major)
@@ -79,6 +79,25 @@ hipError_t launch_radau_group(const DevMech &m, const RadauParams &p, int64_t n,
 int group_max_blocks(int R);
 hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t st);
 size_t group_lds_bytes(int R);
+
+// Predictor network (rk_mlp.hip): FP32 masters, BF16 copy used in products.
+struct Mlp {
+    std::vector<int> dims;
+    float *params = nullptr, *grads = nullptr, *adam_m = nullptr, *adam_v = nullptr, *part = nullptr;
+    uint16_t *wbf = nullptr;
+    std::vector<float *> acts, pre, dacts;   // per layer: post-activation, pre-activation, gradient
+    int64_t cap_b = 0;
+    int steps = 0;
+    ~Mlp();
+    int64_t count() const;
+    hipError_t init(const std::vector<int> &d);
+    hipError_t ensure_batch(int64_t B);
+    hipError_t refresh_bf16(hipStream_t st);
+    hipError_t forward(int64_t B, const float *x, hipStream_t st);
+    hipError_t backward(int64_t B, const float *x, const float *t, const float *mask, const float *wout,
+                        float inv_count, float *loss, hipStream_t st);
+    hipError_t adam(float lr, hipStream_t st);
+};
 
 }  // namespace rk
 

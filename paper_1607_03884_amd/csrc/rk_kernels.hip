@@ -460,7 +460,7 @@ __global__ __launch_bounds__(64) void radau_lane_kernel(DevMech m, LaneLayout L,
             }
             action = ACT_SAME;
             if (nstep >= rp.nmax) { status = RK_ST_STEP_LIMIT; break; }
-            if (h < rp.hmin) { status = RK_ST_H_UNDERFLOW; break; }
+            if (0.1 * h <= kU * t || h < 1e-300) { status = RK_ST_H_UNDERFLOW; break; }   // no longer advances t
             ++nstep;
 
             // starting values: zero on the first step, else the previous step's
