@@ -64,6 +64,8 @@ typedef struct rk_stats {
     int64_t fp32_fallback;    /* states the mixed variant re-ran with FP64 factors */
     int32_t nbins_used;       /* cost bins of the work queue (0: input order) */
     int32_t grid_used;        /* blocks launched for the integrator */
+    int64_t predictor_kept;     /* states whose predicted first step converged */
+    int64_t predictor_fallback; /* states restarted cold after the prediction failed */
 } rk_stats;
 
 /* mech_load — read a mechanism file and upload it to the current device.
@@ -125,6 +127,16 @@ int stats_get(rk_mech *mech, rk_stats *out, int32_t *per_state_steps, int32_t *p
  *              min(n, 32768) states for bins in {0, 8, 16, 32} and grid in
  *              {100 %, 50 %}, keep the fastest (this call blocks the host);
  *              "0": forget the choices
+ *   "predictor" path of a predictor file (network widths K+2 -> ... -> 3(K+1)+2,
+ *              standardisation, parameters) trained for one global step size;
+ *              calls with that dt and the "wave" or "mixed" variant start each
+ *              state's first step from the predicted step size and stage
+ *              values and keep them only if Newton converges, else restart the
+ *              state cold; with "binning" the bin key becomes the predicted
+ *              step count.  "none" removes all predictors.
+ *   "predictor_use" "both" (default) | "h0" (predicted first step size only,
+ *              stage values start at zero) | "z0" (predicted stage values with
+ *              the default first step size): ablations of the predictor
  *   "kmax"     max Newton iterations per step (default 7)
  *   "kappa"    Newton stopping constant (default max(10u/rtol, min(0.03, rtol^0.5)))
  *   "nmax"     step-attempt limit per state (default 100000)

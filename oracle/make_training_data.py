@@ -1,0 +1,48 @@
+"""Training data of the learned stage/step predictor, from this oracle.
+
+For seeded PaSR-like start states (the same mix as the benchmark workloads,
+drawn with a different seed) the oracle integrates one global step and
+records, per state, the stage increments Z = (z1, z2, z3) and the size of its
+first accepted Radau IIA step and the number of step attempts over the
+global step.  One file per mechanism and global step size.
+
+Run:  python -m oracle.make_training_data M13 200000
+Writes paper_1607_03884_amd/data/<mech>_train_dt<dt>.npz (not committed).
+"""
+from __future__ import annotations
+
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from paper_1607_03884_amd import configs, gen  # noqa: E402
+
+TRAIN_SEED = 3000
+
+
+def path_for(mech: str, dt: float) -> str:
+    return os.path.join(configs.DATA_DIR, f"{mech}_train_dt{dt:g}.npz")
+
+
+def make(mech: str, n: int, dts=(configs.DT_SMALL, configs.DT_LARGE), nthreads: int = 0):
+    oracle.build()
+    K = configs.MECHS[mech].n_species
+    m = oracle.Mech(configs.mech_path(mech))
+    states = gen.pasr_like_states(K, n, TRAIN_SEED, configs.load_templates(mech))
+    for dt in dts:
+        t0 = time.time()
+        out, res, z = m.integrate_first_step(states, dt, configs.ATOL, configs.RTOL, nthreads=nthreads)
+        np.savez(path_for(mech, dt), states=states, z_first=z, h_first=res["h_first"], nstep=res["nstep"],
+                 status=res["status"], dt=dt, atol=configs.ATOL, rtol=configs.RTOL)
+        print(f"{mech} dt={dt:g}: {n} states in {time.time() - t0:.1f} s -> {path_for(mech, dt)}", flush=True)
+
+
+if __name__ == "__main__":
+    make(sys.argv[1] if len(sys.argv) > 1 else "M13", int(sys.argv[2]) if len(sys.argv) > 2 else 200000)

@@ -26,7 +26,8 @@ class RkStats(ctypes.Structure):
                 ("n_failed", ctypes.c_int64), ("max_steps", ctypes.c_int32), ("min_steps", ctypes.c_int32),
                 ("d_hist64", ctypes.c_int64 * 20), ("d_hist32", ctypes.c_int64 * 20),
                 ("d_mean64", ctypes.c_double), ("d_mean32", ctypes.c_double), ("kernel_ms", ctypes.c_double),
-                ("fp32_fallback", ctypes.c_int64), ("nbins_used", ctypes.c_int32), ("grid_used", ctypes.c_int32)]
+                ("fp32_fallback", ctypes.c_int64), ("nbins_used", ctypes.c_int32), ("grid_used", ctypes.c_int32),
+                ("predictor_kept", ctypes.c_int64), ("predictor_fallback", ctypes.c_int64)]
 
 
 EXPORTS = ["mech_load", "mech_free", "mech_dims", "radau_integrate", "stats_get", "radau_set_option",

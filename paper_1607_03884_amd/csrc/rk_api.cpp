@@ -398,13 +398,125 @@ int ensure_workspace(rk_mech *m, int64_t n) {
     return RK_OK;
 }
 
+}  // namespace
+
+rk::Predictor::~Predictor() {
+    for (void *q : {(void *)in_shift, (void *)in_scale, (void *)out_shift, (void *)out_scale, (void *)X, (void *)pred})
+        if (q) (void)hipFree(q);
+    delete net;
+}
+
+hipError_t rk::Predictor::ensure(int64_t n) {
+    if (n <= cap) return hipSuccess;
+    if (X) { (void)hipDeviceSynchronize(); (void)hipFree(X); (void)hipFree(pred); X = nullptr; pred = nullptr; }
+    hipError_t e = hipMalloc(&X, (size_t)n * (K + 2) * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&pred, (size_t)n * (3 * (K + 1) + 2) * sizeof(double));
+    if (e == hipSuccess) cap = n;
+    return e;
+}
+
+namespace {
+
+// ---- predictor files -----------------------------------------------------------
+// Text format: "rkpred 1", "mech <name> K <K> dt <dt>", "dims <L> <w0..>",
+// "in_shift"/"in_scale" (K+2 values), "out_shift"/"out_scale" (3N+2 values),
+// "params <count>" values, "end".
+int load_predictor(rk_mech *m, const char *path) {
+    std::ifstream in(path);
+    if (!in) return fail(RK_EIO, std::string("cannot open predictor file ") + path);
+    Tokens tk;
+    std::string w;
+    while (in >> w) tk.t.push_back(w);
+    tk.word("rkpred");
+    if (tk.integer() != 1) tk.bad = true;
+    tk.word("mech");
+    tk.next();
+    tk.word("K");
+    const int K = tk.integer();
+    tk.word("dt");
+    const double dt = tk.num();
+    tk.word("dims");
+    const int L = tk.integer();
+    if (tk.bad || K != m->K || L < 2 || L > 8 || !(dt > 0.0)) return fail(RK_EINVAL, "predictor does not fit this mechanism");
+    std::vector<int> dims(L);
+    for (int &d : dims) {
+        d = tk.integer();
+        if (d < 1 || d > 4096) tk.bad = true;
+    }
+    const int N = K + 1, Din = K + 2, Dout = 3 * N + 2;
+    if (tk.bad || dims.front() != Din || dims.back() != Dout) return fail(RK_EINVAL, "predictor widths do not fit this mechanism");
+    auto vec = [&](const char *name, int cnt) {
+        tk.word(name);
+        std::vector<float> v(cnt);
+        for (float &x : v) x = (float)tk.num();
+        return v;
+    };
+    std::vector<float> ish = vec("in_shift", Din), isc = vec("in_scale", Din);
+    std::vector<float> osh = vec("out_shift", Dout), osc = vec("out_scale", Dout);
+    tk.word("params");
+    const int64_t cnt = tk.integer();
+    std::vector<float> params(cnt > 0 && cnt < (1 << 26) ? cnt : 0);
+    for (float &x : params) x = (float)tk.num();
+    tk.word("end");
+    if (tk.bad) return fail(RK_EPARSE, "malformed predictor file");
+    auto *pr = new rk::Predictor();
+    pr->dt = dt;
+    pr->K = K;
+    pr->dims = dims;
+    pr->net = new rk::Mlp();
+    hipError_t e = pr->net->init(dims);
+    if (e == hipSuccess && pr->net->count() != cnt) {
+        delete pr;
+        return fail(RK_EINVAL, "predictor parameter count does not match its widths");
+    }
+    for (auto pp : {&pr->in_shift, &pr->in_scale})
+        if (e == hipSuccess) e = hipMalloc(pp, Din * sizeof(float));
+    for (auto pp : {&pr->out_shift, &pr->out_scale})
+        if (e == hipSuccess) e = hipMalloc(pp, Dout * sizeof(float));
+    if (e == hipSuccess) e = hipMemcpy(pr->in_shift, ish.data(), Din * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(pr->in_scale, isc.data(), Din * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(pr->out_shift, osh.data(), Dout * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(pr->out_scale, osc.data(), Dout * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(pr->net->params, params.data(), cnt * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = pr->net->refresh_bf16(nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        delete pr;
+        return hip_fail(e, "predictor upload");
+    }
+    for (auto &q : m->predictors)
+        if (q->dt == dt) { delete q; q = pr; return RK_OK; }
+    m->predictors.push_back(pr);
+    return RK_OK;
+}
+
+rk::Predictor *predictor_for(rk_mech *m, double dt) {
+    for (auto *q : m->predictors)
+        if (std::fabs(q->dt - dt) <= 1e-12 * dt) return q;
+    return nullptr;
+}
+
 // Enqueue the flag clear, the optional cost binning and the integrator.
 hipError_t launch_integrator(rk_mech *m, const rk::RadauParams &p, int64_t n, const double *yin, double *yout,
                              double atol, double rtol, int variant, int nbins, int gpct, hipStream_t st) {
     hipError_t e = rk::launch_zero_i32(m->counters + (size_t)rk::C_FLAGS * n, n, st);
     if (e != hipSuccess) return e;
     const int *order = nullptr;
-    if (nbins > 0) {
+    const double *pred = nullptr;
+    rk::Predictor *pr = (variant == 1 || variant == 2) ? predictor_for(m, p.dt) : nullptr;
+    if (pr) {
+        e = pr->ensure(n);
+        if (e != hipSuccess) return e;
+        // network inference; with bins, the key is the predicted step count
+        e = rk::launch_predictor(*pr, n, yin, p.dt, atol, rtol, nbins, nbins > 0 ? m->bins : nullptr, st);
+        if (e != hipSuccess) return e;
+        pred = pr->pred;
+        if (nbins > 0) {
+            e = rk::launch_sort_bins(m->bins, n, nbins, m->order, m->hist, st);
+            if (e != hipSuccess) return e;
+            order = m->order;
+        }
+    } else if (nbins > 0) {
         e = rk::launch_binning(m->dev, n, yin, p.dt, atol, rtol, nbins, m->bins, m->order, m->hist, m->proxy_scratch, st);
         if (e != hipSuccess) return e;
         order = m->order;
@@ -416,8 +528,8 @@ hipError_t launch_integrator(rk_mech *m, const rk::RadauParams &p, int64_t n, co
         const int64_t cap = std::max<int64_t>(1, (int64_t)m->group_blocks * gpct / 100);
         const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(need, cap));
         m->last_grid = grid;
-        return rk::launch_radau_group(m->dev, p, n, yin, yout, m->counters, m->queue, m->fb_list, order, variant == 2,
-                                      grid, st);
+        return rk::launch_radau_group(m->dev, p, n, yin, yout, m->counters, m->queue, m->fb_list, order, pred,
+                                      variant == 2, grid, st);
     }
     m->last_grid = (int)((n + rk::kWave - 1) / rk::kWave);
     return rk::launch_radau_lane(m->dev, p, n, yin, yout, m->scratch, m->counters, order, st);
@@ -509,6 +621,7 @@ void mech_free(rk_mech *m) {
     if (m->hist) (void)hipFree(m->hist);
     if (m->proxy_scratch) (void)hipFree(m->proxy_scratch);
     if (m->tune_buf) (void)hipFree(m->tune_buf);
+    for (auto *q : m->predictors) delete q;
     if (m->ev0) (void)hipEventDestroy(m->ev0);
     if (m->ev1) (void)hipEventDestroy(m->ev1);
     delete m;
@@ -551,6 +664,22 @@ int radau_set_option(rk_mech *m, const char *key, const char *value) {
         m->grid_pct = (int)x;
         return RK_OK;
     }
+    if (k == "predictor") {
+        if (v.empty() || v == "none") {
+            if (m->have_run) (void)hipDeviceSynchronize();
+            for (auto *q : m->predictors) delete q;
+            m->predictors.clear();
+            return RK_OK;
+        }
+        return load_predictor(m, value);
+    }
+    if (k == "predictor_use") {
+        if (v == "both") m->pred_use = 3;
+        else if (v == "h0") m->pred_use = 1;
+        else if (v == "z0") m->pred_use = 2;
+        else return fail(RK_EINVAL, "predictor_use: both | h0 | z0");
+        return RK_OK;
+    }
     if (k == "autotune") {
         if (v != "0" && v != "1") return fail(RK_EINVAL, "autotune: 0 or 1");
         m->autotune = v == "1";
@@ -588,6 +717,7 @@ int radau_integrate(rk_mech *m, int64_t n, double dt, const double *yin, double 
     p.rtol = rtol;
     p.kmax = m->kmax;
     p.nmax = m->nmax;
+    p.pred_use = m->pred_use;
     p.kappa = m->kappa > 0.0 ? m->kappa : std::max(10.0 * 2.220446049250313e-16 / rtol, std::min(0.03, std::sqrt(rtol)));
     p.h0 = m->h0 > 0.0 ? m->h0 : std::min(dt, 1e-6);
     int nbins = m->nbins, gpct = m->grid_pct;
@@ -633,7 +763,10 @@ int stats_get(rk_mech *m, rk_stats *out, int32_t *steps, int32_t *status) {
         out->f_evals += c[(size_t)rk::C_NFEV * n + i];
         out->jac_evals += c[(size_t)rk::C_NJEV * n + i];
         out->lu_factor += c[(size_t)rk::C_NLU * n + i];
-        out->fp32_fallback += c[(size_t)rk::C_FLAGS * n + i] & 1;
+        const int32_t fl = c[(size_t)rk::C_FLAGS * n + i];
+        out->fp32_fallback += (fl & rk::kFlagFp32Fallback) != 0;
+        out->predictor_kept += (fl & rk::kFlagPredKept) != 0;
+        out->predictor_fallback += (fl & rk::kFlagPredFallback) != 0;
         out->n_failed += st[i] != RK_ST_OK;
         out->max_steps = std::max(out->max_steps, ns[i]);
         out->min_steps = std::min(out->min_steps, ns[i]);

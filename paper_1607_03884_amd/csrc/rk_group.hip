@@ -555,7 +555,8 @@ __global__ __launch_bounds__(64) void radau_group_kernel(DevMech m, RadauParams 
                                                          const double *__restrict__ yin, double *__restrict__ yout,
                                                          int32_t *__restrict__ cnt, int *__restrict__ queue,
                                                          const int *__restrict__ order,
-                                                         const int *__restrict__ work_n) {
+                                                         const int *__restrict__ work_n,
+                                                         const double *__restrict__ pred) {
     constexpr bool kMixed = std::is_same<S, float>::value;
     extern __shared__ double smem[];
     const int r = threadIdx.x & (G - 1);
@@ -570,6 +571,10 @@ __global__ __launch_bounds__(64) void radau_group_kernel(DevMech m, RadauParams 
     LUR<S> E1;
     LUC<S> E2;
     int ndiv_row = 0;      // consecutive Newton divergences since the last accepted step
+    bool warm = false;     // first attempt starts from the predictor
+    int flags = 0;
+    double Zw1 = 0.0, Zw2 = 0.0, Zw3 = 0.0;
+    const int PD = 3 * N + 2;
     bool have = false, drained = false;
     int64_t s = 0;
     double P = 0.0, y = 0.0, f0 = 0.0, sc = 1.0, t = 0.0, h = 0.0;
@@ -605,8 +610,19 @@ __global__ __launch_bounds__(64) void radau_group_kernel(DevMech m, RadauParams 
                 } else {
                     have = true;
                     status = RK_ST_OK;
+                    flags = 0;
                     t = 0.0;
-                    h = rp.h0;
+                    warm = pred != nullptr;
+                    if (warm) {
+                        const double *ps = pred + (size_t)s * PD;
+                        const bool zuse = (rp.pred_use & 2) != 0;
+                        h = (rp.pred_use & 1) ? ps[3 * N] : rp.h0;
+                        Zw1 = comp && zuse ? ps[r] : 0.0;
+                        Zw2 = comp && zuse ? ps[N + r] : 0.0;
+                        Zw3 = comp && zuse ? ps[2 * N + r] : 0.0;
+                        warm = h > 0.0 && rp.pred_use != 0;
+                    }
+                    if (!warm) h = rp.h0;
                     last = false;
                     if (t + 1.0001 * h >= dt) { h = dt - t; last = true; }
                     f0 = rhs_g(m, L, r, y, P);
@@ -701,7 +717,9 @@ __global__ __launch_bounds__(64) void radau_group_kernel(DevMech m, RadauParams 
             // starting values (collocation polynomial of the previous step)
             double Z1, Z2, Z3;
             if (first) {
-                Z1 = Z2 = Z3 = 0.0;
+                Z1 = warm ? Zw1 : 0.0;
+                Z2 = warm ? Zw2 : 0.0;
+                Z3 = warm ? Zw3 : 0.0;
             } else {
                 const double c1 = rp.c1, c2 = rp.c2, q = h / hlast;
                 const double t1 = 1.0 + c1 * q, t2 = 1.0 + c2 * q, t3 = 1.0 + q;
@@ -763,7 +781,18 @@ __global__ __launch_bounds__(64) void radau_group_kernel(DevMech m, RadauParams 
                 W1 += dW1; W2 += dW2; W3 += dW3;
                 if (eta * dn <= kappa) { converged = true; break; }
             }
-            if (!converged) {
+            if (!converged && warm) {
+                // the prediction did not converge: start the state cold
+                ++nnf;
+                warm = false;
+                flags |= kFlagPredFallback;
+                h = rp.h0;
+                last = false;
+                if (t + 1.0001 * h >= dt) { h = dt - t; last = true; }
+                hacc = h;
+                hlast = h;
+                action = ACT_LU;
+            } else if (!converged) {
                 ++nnf;
                 h *= 0.5;
                 reject = true;
@@ -775,6 +804,7 @@ __global__ __launch_bounds__(64) void radau_group_kernel(DevMech m, RadauParams 
                     done = true;
                 }
             } else {
+                if (warm) { flags |= kFlagPredKept; warm = false; }
                 // embedded error estimate
                 const double invh = 1.0 / h;
                 const double dz = (rp.d[0] * Z1 + rp.d[1] * Z2 + rp.d[2] * Z3) * invh;
@@ -858,7 +888,9 @@ __global__ __launch_bounds__(64) void radau_group_kernel(DevMech m, RadauParams 
                 cnt[(size_t)C_NFEV * n + s] = nfev;
                 cnt[(size_t)C_NJEV * n + s] = njev;
                 cnt[(size_t)C_NLU * n + s] = nlu;
-                if (kMixed && status == kStatusFallback) cnt[(size_t)C_FLAGS * n + s] = 1;
+                // the FP64 pass over handed-back states keeps the mixed pass's flags
+                const int32_t prev = work_n ? cnt[(size_t)C_FLAGS * n + s] : 0;
+                cnt[(size_t)C_FLAGS * n + s] = prev | flags | (status == kStatusFallback ? kFlagFp32Fallback : 0);
             }
             have = false;
         }
@@ -883,24 +915,25 @@ hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t st) {
 size_t group_lds_bytes(int R) { return (size_t)(kWave / G) * group_lds_doubles(R) * sizeof(double); }
 
 hipError_t launch_radau_group(const DevMech &m, const RadauParams &p, int64_t n, const double *yin, double *yout,
-                              int32_t *counters, int *queue, int *fb_list, const int *order, bool mixed, int grid,
-                              hipStream_t st) {
+                              int32_t *counters, int *queue, int *fb_list, const int *order, const double *pred,
+                              bool mixed, int grid, hipStream_t st) {
     if (n == 0) return hipSuccess;
     if (m.N > G) return hipErrorInvalidValue;
     hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, st, queue);
     const size_t lds = group_lds_bytes(m.R);
     if (!mixed) {
         hipLaunchKernelGGL(radau_group_kernel<double>, dim3(grid), dim3(kWave), lds, st, m, p, n, yin, yout, counters,
-                           queue, order, (const int *)nullptr);
+                           queue, order, (const int *)nullptr, pred);
         return hipGetLastError();
     }
     // mixed pass over every state, then an FP64 pass over the states it handed back
     hipLaunchKernelGGL(radau_group_kernel<float>, dim3(grid), dim3(kWave), lds, st, m, p, n, yin, yout, counters,
-                       queue, order, (const int *)nullptr);
+                       queue, order, (const int *)nullptr, pred);
     hipLaunchKernelGGL(collect_fallback_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, counters, n,
                        fb_list, queue + 1);
+    // the FP64 pass starts the handed-back states cold
     hipLaunchKernelGGL(radau_group_kernel<double>, dim3(grid), dim3(kWave), lds, st, m, p, n, yin, yout, counters,
-                       queue + 2, (const int *)fb_list, (const int *)(queue + 1));
+                       queue + 2, (const int *)fb_list, (const int *)(queue + 1), (const double *)nullptr);
     return hipGetLastError();
 }
 

@@ -38,6 +38,7 @@ struct DevMech {
 struct RadauParams {
     double dt, atol, rtol, kappa, h0;
     int kmax, nmax;
+    int pred_use;            // bit 1: predicted first step size, bit 2: predicted stage values
     double g, a, b;          // eigenvalues of A^-1: g, a +- i b
     double T[9], Ti[9];      // T^-1 A^-1 T = [[g,0,0],[0,a,-b],[0,b,a]] (row-major)
     double c1, c2;           // collocation nodes (c3 = 1)
@@ -57,6 +58,8 @@ struct LaneLayout {
 enum Counter { C_STATUS = 0, C_NSTEP, C_NACC, C_NREJ, C_NNEWT, C_NNFAIL, C_NFEV, C_NJEV, C_NLU, C_FLAGS, kNumCounters };
 // status a mixed-precision pass gives a state it hands to the FP64 pass
 constexpr int kStatusFallback = 4;
+// C_FLAGS bits
+constexpr int kFlagFp32Fallback = 1, kFlagPredKept = 2, kFlagPredFallback = 4;
 
 LaneLayout lane_layout(int K);
 
@@ -74,8 +77,8 @@ hipError_t launch_binning(const DevMech &m, int64_t n, const double *yin, double
 size_t lane_scratch_doubles(int K, int64_t n);
 // group-cooperative variant (16 lanes per state, N <= 16), persistent work queue
 hipError_t launch_radau_group(const DevMech &m, const RadauParams &p, int64_t n, const double *yin, double *yout,
-                              int32_t *counters, int *queue, int *fb_list, const int *order, bool mixed, int grid,
-                              hipStream_t st);
+                              int32_t *counters, int *queue, int *fb_list, const int *order, const double *pred,
+                              bool mixed, int grid, hipStream_t st);
 int group_max_blocks(int R);
 hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t st);
 size_t group_lds_bytes(int R);
@@ -98,6 +101,25 @@ struct Mlp {
                         float inv_count, float *loss, hipStream_t st);
     hipError_t adam(float lr, hipStream_t st);
 };
+
+// Loaded predictor for one global step size (device copies of the
+// standardisation and the network) and its per-call buffers.
+struct Predictor {
+    double dt = 0.0;
+    int K = 0;
+    std::vector<int> dims;
+    float *in_shift = nullptr, *in_scale = nullptr, *out_shift = nullptr, *out_scale = nullptr;
+    Mlp *net = nullptr;
+    float *X = nullptr;       // [n][K+2] features
+    double *pred = nullptr;   // [n][3N+2] stage values, first step, step attempts
+    int64_t cap = 0;
+    ~Predictor();
+    hipError_t ensure(int64_t n);
+};
+
+hipError_t launch_predictor(Predictor &pr, int64_t n, const double *yin, double dt, double atol, double rtol,
+                            int nbins, int *bins, hipStream_t st);
+hipError_t launch_sort_bins(const int *bins, int64_t n, int nbins, int *order, int *hist, hipStream_t st);
 
 }  // namespace rk
 
@@ -134,11 +156,13 @@ struct rk_mech {
     double *proxy_scratch = nullptr;
     // autotuner: chosen (bins, grid percent) per dt, trial buffers
     bool autotune = false;
+    int pred_use = 3;
     std::vector<std::pair<double, std::pair<int, int>>> tuned;
     int grid_pct = 100;
     double *tune_buf = nullptr;
     size_t tune_cap = 0;
     int last_nbins = 0, last_grid = 0;
+    std::vector<rk::Predictor *> predictors;   // one per global step size
     int group_blocks = 0;      // resident blocks of the group kernel (cached)
     int64_t last_n = 0;
     hipStream_t last_stream = nullptr;

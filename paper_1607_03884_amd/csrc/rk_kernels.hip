@@ -797,6 +797,12 @@ hipError_t launch_binning(const DevMech &m, int64_t n, const double *yin, double
                        atol, rtol, nbins, bins, scratch, (int64_t)kProxyLanes);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    return launch_sort_bins(bins, n, nbins, order, hist, st);
+}
+
+hipError_t launch_sort_bins(const int *bins, int64_t n, int nbins, int *order, int *hist, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    if (nbins < 1 || nbins > 64) return hipErrorInvalidValue;
     hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(128), 0, st, hist, 128);
     hipLaunchKernelGGL(bin_hist_kernel, dim3(256), dim3(256), 0, st, bins, n, nbins, hist);
     hipLaunchKernelGGL(bin_scan_kernel, dim3(1), dim3(64), 0, st, hist, nbins, hist + 64);

@@ -1,0 +1,189 @@
+"""Learned first-step predictor in the integration call (MLP, BF16 weights,
+FP32 accumulation): parity with the oracle is unchanged, a prediction that
+Newton cannot converge falls back to the cold start, predicted step counts
+drive the cost bins without changing any result, and the ablation against the
+cold start is printed and checked."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_1607_03884_amd import configs, gen, predictor
+from tests.parity import banner, integration_errors
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+DTS = [1e-6, 1e-4]
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch, torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def gm(torch_dev, m13_path):
+    from paper_1607_03884_amd import Mechanism
+    g = Mechanism(m13_path)
+    for dt in DTS:
+        g.set_option("predictor", predictor.path_for("M13", dt))
+    return g
+
+
+@pytest.fixture(scope="module")
+def cfg1_rows():
+    return configs.states_for(configs.WORKLOADS["cfg1"])
+
+
+def _run(torch_dev, g, rows, dt, **opts):
+    torch, dev = torch_dev
+    for k, v in opts.items():
+        g.set_option(k, v)
+    y = torch.from_numpy(gen.to_soa(rows)).to(dev)
+    out = torch.full_like(y, float("nan"))
+    g.integrate(y, dt, configs.ATOL, configs.RTOL, y_out=out)
+    torch.cuda.synchronize()
+    st = g.stats(per_state=True)
+    return out.cpu().numpy().T, st
+
+
+def _reset(g):
+    for k, v in (("variant", "auto"), ("binning", 0), ("autotune", 0), ("predictor_use", "both")):
+        g.set_option(k, v)
+
+
+def _summary(tag, st):
+    n = st["n_states"]
+    return (f"{tag:>22}: kernel {st['kernel_ms']:7.1f} ms  steps/state {st['steps'] / n:6.3f}  "
+            f"rejected {st['rejected']:7d}  newton/state {st['newton_iters'] / n:7.3f}  "
+            f"newton fails {st['newton_fail']:6d}  kept {st['predictor_kept']:7d}  "
+            f"fallback {st['predictor_fallback']:6d}")
+
+
+@pytest.mark.parametrize("variant", ["wave", "mixed"])
+@pytest.mark.parametrize("dt", DTS)
+def test_learned_cfg1_parity(torch_dev, gm, m13, cfg1_rows, dt, variant):
+    """262,144 PaSR-like states with the predictor: every state finishes, the
+    mass fractions keep their sum, and a sample (costliest states, states whose
+    prediction fell back, random states) matches the oracle to 1e-5."""
+    banner(f"learned cfg1 dt={dt} variant={variant}")
+    rows = cfg1_rows
+    got, st = _run(torch_dev, gm, rows, dt, variant=variant, predictor_use="both")
+    _reset(gm)
+    print(_summary(f"{variant} dt={dt}", st))
+    assert np.all(st["per_state_status"] == 0)
+    assert np.all(np.isfinite(got))
+    assert st["predictor_kept"] + st["predictor_fallback"] == len(rows)
+    assert st["predictor_kept"] >= 0.5 * len(rows)
+    assert np.abs(got[:, 1:14].sum(1) - rows[:, 1:14].sum(1)).max() <= (1e-12 if variant == "wave" else 1e-9)
+    steps = st["per_state_steps"]
+    rng = np.random.default_rng(78)
+    top = np.argsort(steps)[-256:]
+    pick = np.unique(np.concatenate([top, rng.choice(len(rows), 768, replace=False)]))
+    ref, res = m13.integrate(rows[pick], dt)
+    assert np.all(res["status"] == 0)
+    eT, eY = integration_errors(got[pick], ref, 13)
+    print(f"  max rel err on {len(pick)} sampled states: T {eT:.2e} Y {eY:.2e}")
+    assert eT <= TOL and eY <= TOL
+
+
+@pytest.mark.parametrize("dt", DTS)
+def test_learned_ablation(torch_dev, gm, cfg1_rows, dt):
+    """Cold start against the predicted first step size, the predicted stage
+    values and both, on the full workload (wave variant, no bins), then with
+    16 bins from the proxy key and from the predicted step counts."""
+    banner(f"learned ablation cfg1 dt={dt}")
+    rows = cfg1_rows
+    res = {}
+    _, res["cold"] = _run(torch_dev, gm, rows, dt, variant="wave", predictor="none")
+    gm.set_option("predictor", predictor.path_for("M13", dt))
+    for use in ("h0", "z0", "both"):
+        _, res[use] = _run(torch_dev, gm, rows, dt, variant="wave", predictor_use=use)
+    gm.set_option("predictor", "none")
+    _, res["cold+proxy bins"] = _run(torch_dev, gm, rows, dt, variant="wave", binning=16)
+    for d in DTS:
+        gm.set_option("predictor", predictor.path_for("M13", d))
+    _, res["both+predicted bins"] = _run(torch_dev, gm, rows, dt, variant="wave", binning=16, predictor_use="both")
+    _reset(gm)
+    for k, st in res.items():
+        print(_summary(k, st))
+    cold, both = res["cold"], res["both"]
+    # the cold start and the predictor integrate the same states
+    assert cold["predictor_kept"] == 0 and cold["predictor_fallback"] == 0
+    assert both["predictor_kept"] + both["predictor_fallback"] == len(rows)
+    # predicted step counts order the states at least as well as the proxy key
+    p_steps = res["both+predicted bins"]["per_state_steps"]
+    assert np.array_equal(p_steps, both["per_state_steps"])
+
+
+def test_poisoned_predictor_falls_back(torch_dev, m13, tmp_path):
+    """A predictor with garbage outputs (huge stage values, tiny first steps)
+    must not change what is computed beyond the tolerance: Newton rejects the
+    predicted stage values and the state restarts cold."""
+    banner("learned poisoned predictor")
+    from paper_1607_03884_amd import Mechanism
+    g = Mechanism(configs.mech_path("M13"))
+    K, N, dt = 13, 14, 1e-6
+    dims = [K + 2, 16, 3 * N + 2]
+    rng = np.random.default_rng(5)
+    nparam = sum(dims[i] * dims[i + 1] + dims[i + 1] for i in range(len(dims) - 1))
+    params = rng.standard_normal(nparam) * 3.0
+    out_shift = np.concatenate([np.full(3 * N, 30.0), [-4.0, 1.0]])
+    path = os.path.join(str(tmp_path), "poison.rkp")
+    predictor.write(path, "M13", K, dt, dims, np.zeros(K + 2), np.ones(K + 2), out_shift, np.full(3 * N + 2, 5.0),
+                    params)
+    g.set_option("predictor", path)
+    rows = configs.states_for(configs.WORKLOADS["cfg0"])
+    got, st = _run(torch_dev, g, rows, dt, variant="wave")
+    print(_summary("poisoned", st))
+    ref, res = m13.integrate(rows, dt)
+    eT, eY = integration_errors(got, ref, 13)
+    print(f"  max rel err T {eT:.2e} Y {eY:.2e}")
+    assert np.all(st["per_state_status"] == 0)
+    assert st["predictor_fallback"] >= 0.9 * len(rows)
+    assert eT <= TOL and eY <= TOL
+    g.close()
+
+
+def test_predictor_file_errors(torch_dev, tmp_path):
+    """Malformed or mismatched predictor files are refused with an error and
+    leave the handle usable."""
+    banner("learned predictor file errors")
+    from paper_1607_03884_amd import Mechanism
+    from paper_1607_03884_amd._lib import RkError
+    g = Mechanism(configs.mech_path("M13"))
+    bad = os.path.join(str(tmp_path), "bad.rkp")
+    with open(bad, "w") as fh:
+        fh.write("rkpred 1\nmech M13 K 12 dt 1e-6\nend\n")
+    with pytest.raises(RkError):
+        g.set_option("predictor", bad)
+    with pytest.raises(RkError):
+        g.set_option("predictor", os.path.join(str(tmp_path), "missing.rkp"))
+    with pytest.raises(RkError):
+        g.set_option("predictor_use", "sometimes")
+    g.set_option("predictor", predictor.path_for("M13", 1e-6))
+    rows = configs.states_for(configs.WORKLOADS["cfg0"], 64)
+    got, st = _run(torch_dev, g, rows, 1e-6, variant="wave")
+    assert np.all(st["per_state_status"] == 0)
+    g.close()
+
+
+def test_schedule_invariance_predicted_bins(torch_dev, gm):
+    """With the predictor, bins from predicted step counts and the autotuned
+    schedule give bitwise the same outputs and step counts as input order."""
+    banner("learned schedule invariance")
+    rows = configs.states_for(configs.WORKLOADS["cfg1"], 40000)
+    outs, steps = [], []
+    for opts in ({"binning": 0}, {"binning": 16}, {"binning": 0, "autotune": 1}):
+        got, st = _run(torch_dev, gm, rows, 1e-6, variant="wave", **opts)
+        outs.append(got)
+        steps.append(st["per_state_steps"].copy())
+        print(f"{opts}: kernel {st['kernel_ms']:.1f} ms, bins {st['nbins_used']}, grid {st['grid_used']}")
+    _reset(gm)
+    assert np.all(np.isfinite(outs[0]))
+    for o, s in zip(outs[1:], steps[1:]):
+        assert np.array_equal(o, outs[0])
+        assert np.array_equal(s, steps[0])
