@@ -44,11 +44,12 @@ class Result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("nstep", ctypes.c_int32), ("naccept", ctypes.c_int32),
                 ("nreject", ctypes.c_int32), ("nnewton", ctypes.c_int32), ("nnewtfail", ctypes.c_int32),
                 ("nfev", ctypes.c_int32), ("njev", ctypes.c_int32), ("nlu", ctypes.c_int32),
-                ("h_first", ctypes.c_double)]
+                ("warm", ctypes.c_int32), ("h_first", ctypes.c_double)]
 
 
 RESULT_DTYPE = np.dtype([(n, np.int32) for n in ("status", "nstep", "naccept", "nreject", "nnewton",
-                                                 "nnewtfail", "nfev", "njev", "nlu")] + [("h_first", np.float64)],
+                                                 "nnewtfail", "nfev", "njev", "nlu", "warm")] +
+                        [("h_first", np.float64)],
                         align=True)
 
 _lib = None
@@ -78,6 +79,9 @@ def lib():
                                          ctypes.c_double, ctypes.c_double, ctypes.POINTER(Opts), dp,
                                          ctypes.c_void_p, ctypes.c_int]
         L.or_integrate_batch2.argtypes = L.or_integrate_batch.argtypes + [dp]
+        L.or_integrate_batch3.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, dp, dp,
+                                          ctypes.c_double, ctypes.c_double, ctypes.POINTER(Opts), dp, dp,
+                                          ctypes.c_void_p, ctypes.c_int, dp]
         L.or_integrate_linear.argtypes = [ctypes.c_int, dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                           ctypes.POINTER(Opts), dp, ctypes.POINTER(Result), dp, ctypes.c_int]
         L.or_fixed_steps.argtypes = [ctypes.c_void_p, dp, ctypes.c_double, ctypes.c_int, dp]
@@ -169,6 +173,31 @@ class Mech:
             h0p = _p(h0)
         lib().or_integrate_batch(self.h, n, dt, _p(st), _p(out), atol, rtol, ctypes.byref(o), h0p,
                                  res.ctypes.data_as(ctypes.c_void_p), nthreads)
+        return out, res
+
+    def integrate_warm(self, states: np.ndarray, dt: float, hw: Optional[np.ndarray], zw: Optional[np.ndarray],
+                       atol: float = 1e-10, rtol: float = 1e-6, opts: Optional[Opts] = None, nthreads: int = 0):
+        """Integration with a per-state warm start for the first step attempt:
+        step size hw [n] (<= 0 or None: the default rule) and Newton starting
+        values zw [n, 3, N] (None: zero); a warm attempt whose Newton iteration
+        does not converge restarts the state cold.  res["warm"]: 1 kept,
+        2 restarted cold."""
+        st = np.ascontiguousarray(states, dtype=np.float64)
+        n = st.shape[0]
+        out = np.zeros_like(st)
+        res = np.zeros(n, dtype=RESULT_DTYPE)
+        o = opts or default_opts()
+        hwp = zwp = None
+        if hw is not None:
+            hw = np.ascontiguousarray(hw, dtype=np.float64)
+            assert hw.shape == (n,)
+            hwp = _p(hw)
+        if zw is not None:
+            zw = np.ascontiguousarray(zw, dtype=np.float64)
+            assert zw.shape == (n, 3, self.N)
+            zwp = _p(zw)
+        lib().or_integrate_batch3(self.h, n, dt, _p(st), _p(out), atol, rtol, ctypes.byref(o), hwp, zwp,
+                                  res.ctypes.data_as(ctypes.c_void_p), nthreads, None)
         return out, res
 
     def integrate_first_step(self, states: np.ndarray, dt: float, atol: float = 1e-10, rtol: float = 1e-6,

@@ -66,6 +66,7 @@ typedef struct {
     int32_t status;
     int32_t nstep;            /* step attempts (Newton started) */
     int32_t naccept, nreject, nnewton, nnewtfail, nfev, njev, nlu;
+    int32_t warm;             /* warm start: 0 none, 1 kept, 2 Newton failed -> cold restart */
     double h_first;           /* size of the first accepted step */
 } or_result;
 
@@ -107,6 +108,16 @@ int or_integrate_batch(const or_mech *m, int64_t n, double dt, const double *y_i
  * of each state's first accepted step in zfirst[n][3N] (may be NULL) */
 int or_integrate_batch2(const or_mech *m, int64_t n, double dt, const double *y_in, double *y_out,
                         double atol, double rtol, const or_opts *o, const double *h0,
+                        or_result *res, int nthreads, double *zfirst);
+
+/* as or_integrate_batch2, with an optional warm start per state: the first
+ * step attempt uses step size hw[i] (<= 0: the default rule) and Newton
+ * starting values zw[i][3N] (NULL: zero).  If Newton does not converge on
+ * that attempt the state restarts exactly as a cold start (default initial
+ * step, zero starting values, controller memory reset).  hw or zw may be NULL;
+ * a state is warm if hw[i] > 0 or zw is given. */
+int or_integrate_batch3(const or_mech *m, int64_t n, double dt, const double *y_in, double *y_out,
+                        double atol, double rtol, const or_opts *o, const double *hw, const double *zw,
                         or_result *res, int nthreads, double *zfirst);
 
 /* Radau IIA on the linear system y' = M y (row-major N x N), for the

@@ -183,7 +183,8 @@ static int finite_vec(const double *v, int n) {
 
 /* Integrate y over [0, dt] in place. */
 static int radau_core(const problem *pb, double dt, double *y, double atol, double rtol, const or_opts *o,
-                      double h0, or_result *res, double *hrec, int cap, double *zfirst) {
+                      double h0, int warm, const double *zw, or_result *res, double *hrec, int cap,
+                      double *zfirst) {
     const int N = pb->N, N3 = 3 * N;
     rconst k;
     radau_consts(&k);
@@ -209,7 +210,8 @@ static int radau_core(const problem *pb, double dt, double *y, double atol, doub
     if (!finite_vec(y, N)) { res->status = OR_NONFINITE; goto done; }
 
     double t = 0.0;
-    double h = h0 > 0 ? h0 : (o->h0 > 0 ? o->h0 : fmin(dt, 1e-6));
+    const double hcold = o->h0 > 0 ? o->h0 : fmin(dt, 1e-6);
+    double h = h0 > 0 ? h0 : hcold;
     int last = 0;
     if (t + 1.0001 * h >= dt) { h = dt - t; last = 1; }
     pb->f(pb->ctx, y, f0); res->nfev++;
@@ -245,7 +247,8 @@ static int radau_core(const problem *pb, double dt, double *y, double atol, doub
          * step's collocation cubic q (q(0)=0, q(c_i)=z_i) evaluated at the new
          * stage abscissae, tau = 1 + c_i h/h_old, minus q(1) = z_3 */
         if (first) {
-            memset(Z, 0, sizeof(double) * N3);
+            if (warm && zw) memcpy(Z, zw, sizeof(double) * N3);
+            else memset(Z, 0, sizeof(double) * N3);
         } else {
             double tn[4] = { 0.0, k.c[0], k.c[1], 1.0 };
             for (int i = 0; i < 3; ++i) {
@@ -314,6 +317,23 @@ static int radau_core(const problem *pb, double dt, double *y, double atol, doub
                 W[i * N + c] = k.Ti[i * 3] * Z[c] + k.Ti[i * 3 + 1] * Z[N + c] + k.Ti[i * 3 + 2] * Z[2 * N + c];
             if (eta * dn <= kappa) { converged = 1; break; }
         }
+        if (!converged && warm) {
+            /* the warm start did not converge: restart as a cold start */
+            res->nnewtfail++;
+            res->warm = 2;
+            warm = 0;
+            h = hcold;
+            last = 0;
+            if (t + 1.0001 * h >= dt) { h = dt - t; last = 1; }
+            eta = 1.0;
+            theta = 1.0;
+            hacc = h;
+            erracc = 1e-2;
+            hlast = h;
+            action = NEW_LU;
+            continue;
+        }
+        if (warm) { res->warm = 1; warm = 0; }
         if (!converged) {
             /* (reading) Newton failure: halve h and redo; fresh J if stale */
             res->nnewtfail++;
@@ -415,9 +435,9 @@ static void chem_j(void *c, const double *y, double *J) {
     if (x->iso) or_jac_iso(x->m, y, x->P, J); else or_jac(x->m, y, x->P, J);
 }
 
-int or_integrate_batch2(const or_mech *m, int64_t n, double dt, const double *y_in, double *y_out,
-                        double atol, double rtol, const or_opts *o, const double *h0,
-                        or_result *res, int nthreads, double *zfirst) {
+static int integrate_rows(const or_mech *m, int64_t n, double dt, const double *y_in, double *y_out,
+                          double atol, double rtol, const or_opts *o, const double *h0, int warm_h,
+                          const double *zw, or_result *res, int nthreads, double *zfirst) {
     const int K = m->K, N = K + 1, S = K + 2;
     or_opts dflt;
     if (!o) { or_default_opts(&dflt); o = &dflt; }
@@ -440,7 +460,9 @@ int or_integrate_batch2(const or_mech *m, int64_t n, double dt, const double *y_
             res[i].status = OR_NONFINITE;
             memcpy(out, row, sizeof(double) * S);
         } else {
-            radau_core(&pb, dt, y, atol, rtol, o, h0 ? h0[i] : 0.0, &res[i], NULL, 0,
+            const double hi = h0 ? h0[i] : 0.0;
+            const int warm = warm_h ? (hi > 0.0 || zw != NULL) : 0;
+            radau_core(&pb, dt, y, atol, rtol, o, hi, warm, zw ? zw + i * 3 * N : NULL, &res[i], NULL, 0,
                        zfirst ? zfirst + i * 3 * N : NULL);
             memcpy(out, y, sizeof(double) * N);
             out[K + 1] = row[K + 1];
@@ -448,6 +470,18 @@ int or_integrate_batch2(const or_mech *m, int64_t n, double dt, const double *y_
         free(y);
     }
     return 0;
+}
+
+int or_integrate_batch2(const or_mech *m, int64_t n, double dt, const double *y_in, double *y_out,
+                        double atol, double rtol, const or_opts *o, const double *h0,
+                        or_result *res, int nthreads, double *zfirst) {
+    return integrate_rows(m, n, dt, y_in, y_out, atol, rtol, o, h0, 0, NULL, res, nthreads, zfirst);
+}
+
+int or_integrate_batch3(const or_mech *m, int64_t n, double dt, const double *y_in, double *y_out,
+                        double atol, double rtol, const or_opts *o, const double *hw, const double *zw,
+                        or_result *res, int nthreads, double *zfirst) {
+    return integrate_rows(m, n, dt, y_in, y_out, atol, rtol, o, hw, 1, zw, res, nthreads, zfirst);
 }
 
 typedef struct { int N; const double *M; } lin_ctx;
@@ -468,7 +502,7 @@ int or_integrate_linear(int N, const double *M, const double *y0, double dt, dou
     lin_ctx cx = { N, M };
     problem pb = { N, lin_f, lin_j, &cx };
     memcpy(y_out, y0, sizeof(double) * N);
-    return radau_core(&pb, dt, y_out, atol, rtol, o, 0.0, res, hrec, cap, NULL);
+    return radau_core(&pb, dt, y_out, atol, rtol, o, 0.0, 0, NULL, res, hrec, cap, NULL);
 }
 
 int or_integrate_batch(const or_mech *m, int64_t n, double dt, const double *y_in, double *y_out,

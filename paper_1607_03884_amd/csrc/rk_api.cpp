@@ -523,8 +523,9 @@ hipError_t launch_integrator(rk_mech *m, const rk::RadauParams &p, int64_t n, co
     }
     m->last_nbins = nbins;
     if (variant == 1 || variant == 2) {
-        if (m->group_blocks == 0) m->group_blocks = rk::group_max_blocks(m->R);
-        const int64_t need = (n + 3) / 4;
+        if (m->group_blocks == 0) m->group_blocks = rk::group_max_blocks(m->K + 1, m->R);
+        const int spb = rk::group_states_per_block(m->K + 1);
+        const int64_t need = (n + spb - 1) / spb;
         const int64_t cap = std::max<int64_t>(1, (int64_t)m->group_blocks * gpct / 100);
         const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(need, cap));
         m->last_grid = grid;
@@ -536,13 +537,14 @@ hipError_t launch_integrator(rk_mech *m, const rk::RadauParams &p, int64_t n, co
 }
 
 // Scheduling autotuner: times the integrator on the first min(n, 32768) states
-// (compacted) for every (bin count, persistent-grid size) candidate and keeps
+// (8192 for mechanisms with more than 15 species), compacted, for every
+// (bin count, persistent-grid size) candidate and keeps
 // the fastest for this dt.  Runs once per (handle, dt); blocks the host.
 int autotune(rk_mech *m, int64_t n, double dt, const double *yin, double atol, double rtol, hipStream_t st,
              const rk::RadauParams &p, int variant, int &nbins, int &gpct) {
     for (auto &t : m->tuned)
         if (t.first == dt) { nbins = t.second.first; gpct = t.second.second; return RK_OK; }
-    const int64_t ms = std::min<int64_t>(n, 32768);
+    const int64_t ms = std::min<int64_t>(n, m->K + 1 <= 16 ? 32768 : 8192);   // bounded trial cost
     const int rows = m->K + 2;
     const size_t need = (size_t)ms * rows * 2;
     if (need > m->tune_cap) {
@@ -703,10 +705,10 @@ int radau_integrate(rk_mech *m, int64_t n, double dt, const double *yin, double 
     if (n > 0 && (!yin || !yout)) return fail(RK_EINVAL, "radau_integrate: NULL state pointer");
     if (n > 0 && (!is_device_ptr(yin) || !is_device_ptr(yout)))
         return fail(RK_EINVAL, "radau_integrate: state arrays must be device memory");
-    const bool group_ok = m->K + 1 <= 16 && rk::group_lds_bytes(m->R) <= 65536;
+    const bool group_ok = rk::group_supported(m->K + 1) && rk::group_lds_bytes(m->K + 1, m->R) <= 65536;
     const int variant = m->variant >= 0 ? m->variant : (group_ok ? 1 : 0);
     if ((variant == 1 || variant == 2) && !group_ok)
-        return fail(RK_EINVAL, "radau_integrate: the wave and mixed variants need K + 1 <= 16 and fewer than 2000 reactions");
+        return fail(RK_EINVAL, "radau_integrate: the wave and mixed variants need K + 1 <= 56");
     int rc = ensure_workspace(m, std::max<int64_t>(n, 1));
     if (rc != RK_OK) return rc;
     hipStream_t st = static_cast<hipStream_t>(stream);

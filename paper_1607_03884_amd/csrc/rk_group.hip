@@ -1,15 +1,17 @@
-// Radau IIA with a group of 16 lanes cooperating on one state (the paper's
-// per-block pattern, Sec. 1.2, sized to a quarter wavefront), for mechanisms
-// with N = K + 1 <= 16 unknowns.
+// Radau IIA with a group of G lanes cooperating on one state (the paper's
+// per-block pattern, Sec. 1.2): G = 16 (a quarter wavefront, four states per
+// wavefront) for mechanisms with N = K + 1 <= 16 unknowns, G = 64 (one state
+// per wavefront) for N <= 56.
 //
 // Lane r of a group owns component r of every vector (r = 0 temperature,
 // r = 1..K mass fractions) and row r of the iteration matrices.  The LU
-// factors of E1 (real) and E2 (complex) stay in registers: partial pivoting
-// is done by row ownership (the pivot row is chosen among the rows not yet
-// used, its lane records the elimination position, nothing moves), so every
-// register index is a compile-time constant.  Per-species and per-reaction
-// intermediates of the source terms and of the Jacobian go through the
-// group's slice of LDS; J itself is assembled and kept in LDS.
+// factors of E1 (real) and E2 (complex) stay in registers (NC columns per
+// row): partial pivoting is done by row ownership (the pivot row is chosen
+// among the rows not yet used, its lane records the elimination position,
+// nothing moves), so every register index is a compile-time constant.
+// Per-species and per-reaction intermediates of the source terms and of the
+// Jacobian go through the group's slice of LDS, the reactions in chunks of at
+// most 64; J itself is assembled and kept in LDS.
 //
 // Work distribution: a persistent grid whose groups pull states from a device
 // queue (one atomic per state), so a group that finishes a cheap state starts
@@ -27,14 +29,14 @@ namespace rk {
 
 namespace {
 
-constexpr int G = 16;                          // lanes per state = max N
 constexpr double kU = 2.220446049250313e-16;
 
 __device__ __forceinline__ void sync_wave() { __syncthreads(); }   // blocks are one wavefront
 
 // In-row (16-lane) data-parallel moves.  Every reduction below gives the same
-// bits in all 16 lanes (pairwise combinations of equal operands), so group
-// control decisions taken on reduced values are uniform within the group.
+// bits in all lanes of the group (pairwise combinations of equal operands, then
+// a fixed-order combination of the four rows for G = 64), so group control
+// decisions taken on reduced values are uniform within the group.
 template <int CTRL>
 __device__ __forceinline__ double dpp(double v) {
     const uint64_t u = __builtin_bit_cast(uint64_t, v);
@@ -50,50 +52,83 @@ __device__ __forceinline__ uint64_t dppu(uint64_t u) {
 }
 constexpr int kRowMirror = 0x140, kRowHalfMirror = 0x141, kQuadXor2 = 0x4E, kQuadXor1 = 0xB1;
 
+// value of a lane of the wavefront (wave-uniform result)
+__device__ __forceinline__ uint64_t rlaneu(uint64_t u, int lane) {
+    const int lo = __builtin_amdgcn_readlane((int)(uint32_t)u, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), lane);
+    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+__device__ __forceinline__ double rlane(double v, int lane) {
+    return __builtin_bit_cast(double, rlaneu(__builtin_bit_cast(uint64_t, v), lane));
+}
+__device__ __forceinline__ float rlane(float v, int lane) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+}
+
+template <int G>
 __device__ __forceinline__ double gsum(double v) {
     v = v + dpp<kRowMirror>(v);        // lanes i, 15-i
     v = v + dpp<kRowHalfMirror>(v);    // ... and 7-i, 8+i (within each half)
     v = v + dpp<kQuadXor2>(v);
     v = v + dpp<kQuadXor1>(v);
+    if constexpr (G == 64) v = (rlane(v, 0) + rlane(v, 16)) + (rlane(v, 32) + rlane(v, 48));
     return v;
 }
 
+template <int G>
 __device__ __forceinline__ uint64_t gmaxu(uint64_t v) {
     uint64_t o;
     o = dppu<kRowMirror>(v); v = o > v ? o : v;
     o = dppu<kRowHalfMirror>(v); v = o > v ? o : v;
     o = dppu<kQuadXor2>(v); v = o > v ? o : v;
     o = dppu<kQuadXor1>(v); v = o > v ? o : v;
+    if constexpr (G == 64) {
+        const uint64_t a = rlaneu(v, 0), b = rlaneu(v, 16), c = rlaneu(v, 32), d = rlaneu(v, 48);
+        const uint64_t ab = a > b ? a : b, cd = c > d ? c : d;
+        v = ab > cd ? ab : cd;
+    }
     return v;
 }
 
+template <int G>
 __device__ __forceinline__ double gb(double v, int src) { return __shfl(v, src, G); }
+template <int G>
+__device__ __forceinline__ float gb(float v, int src) { return __shfl(v, src, G); }
+template <int G>
 __device__ __forceinline__ int gbi(int v, int src) { return __shfl(v, src, G); }
 
 // Pivot choice: lane whose non-negative magnitude is largest; key = magnitude
-// bits with the 4 low mantissa bits replaced by (15 - lane), so equal
+// bits with the log2(G) low mantissa bits replaced by (G - 1 - lane), so equal
 // magnitudes go to the lowest lane; rows already used carry key 0.
+template <int G>
 __device__ __forceinline__ int gpivot(double mag, bool used, int lane) {
-    const uint64_t key = used ? 0ull : ((__builtin_bit_cast(uint64_t, mag) & ~0xFull) | (uint64_t)(15 - lane));
-    return 15 - (int)(gmaxu(key) & 0xF);
+    constexpr uint64_t kMask = G - 1;
+    const uint64_t key = used ? 0ull : ((__builtin_bit_cast(uint64_t, mag) & ~kMask) | (uint64_t)(kMask - lane));
+    return (int)kMask - (int)(gmaxu<G>(key) & kMask);
 }
 
-// LDS slice of one group (doubles)
+// LDS slice of one group (doubles).  J is row-major with an odd leading
+// dimension NC + 1, so lanes reading down a column hit distinct banks.
 struct GL {
     double *C, *h, *s, *rec, *J, *prow, *vx;
 };
 
-__host__ __device__ constexpr int group_lds_doubles(int R) { return 3 * G + 8 * R + G * G + 2 * G + 4 * G; }
+__host__ __device__ constexpr int rec_chunk(int R) { return R < 64 ? R : 64; }
 
+__host__ __device__ constexpr int group_lds_doubles(int NC, int R) {
+    return 3 * NC + 8 * rec_chunk(R) + NC * (NC + 1) + 2 * NC + NC;
+}
+
+template <int NC>
 __device__ __forceinline__ GL group_lds(double *base, int R) {
     GL L;
     L.C = base;
-    L.h = base + G;
-    L.s = base + 2 * G;
-    L.rec = base + 3 * G;
-    L.J = L.rec + 8 * R;
-    L.prow = L.J + G * G;
-    L.vx = L.prow + 2 * G;
+    L.h = base + NC;
+    L.s = base + 2 * NC;
+    L.rec = base + 3 * NC;
+    L.J = L.rec + 8 * rec_chunk(R);
+    L.prow = L.J + NC * (NC + 1);
+    L.vx = L.prow + 2 * NC;
     return L;
 }
 
@@ -189,14 +224,15 @@ struct Mix {
 };
 
 // mixture quantities and concentrations/thermo into LDS; returns lane data
+template <int G>
 __device__ __forceinline__ Mix mixture(const DevMech &m, const GL &L, int r, double yv, double P, Thermo &th) {
     Mix x;
-    x.T = gb(yv, 0);
+    x.T = gb<G>(yv, 0);
     x.k = r - 1;
     x.isY = r >= 1 && r <= m.K;
     x.Y = x.isY ? yv : 0.0;
     x.invW = x.isY ? m.invW[x.k] : 0.0;
-    const double sumYW = gsum(x.Y * x.invW);
+    const double sumYW = gsum<G>(x.Y * x.invW);
     x.Wbar = 1.0 / sumYW;
     x.rho = P * x.Wbar / (kRu * x.T);
     x.lnT = log(x.T);
@@ -215,101 +251,117 @@ __device__ __forceinline__ Mix mixture(const DevMech &m, const GL &L, int r, dou
     return x;
 }
 
-// f(y): lane r in, lane r out
-__device__ double rhs_g(const DevMech &m, const GL &L, int r, double yv, double P) {
+// f(y): lane r in, lane r out.  Reaction rates of one chunk go to LDS, then
+// each species lane adds its entries of that chunk in reaction order.
+template <int G>
+__device__ __forceinline__ double rhs_g(const DevMech &m, const GL &L, int r, double yv, double P) {
     Thermo th;
-    const Mix x = mixture(m, L, r, yv, P, th);
-    for (int j = r; j < m.R; j += G) {
-        const RxEval e = eval_reaction(m, L, j, x.T, x.lnT, x.invT, x.lnPRT, false);
-        double q = e.kf * e.Pf - e.kr * e.Pp;
-        if (e.kind == 1) q *= e.Mc;
-        L.rec[8 * j] = q;
-    }
-    sync_wave();
+    const Mix x = mixture<G>(m, L, r, yv, P, th);
+    const int R = m.R, CH = rec_chunk(R);
     double wdot = 0.0;
-    if (x.isY)
-        for (int i = m.sp_off[x.k]; i < m.sp_off[x.k + 1]; ++i) {
-            const int2 e = m.sp_rx[i];
-            wdot += e.y * L.rec[8 * e.x];
+    int i = x.isY ? m.sp_off[x.k] : 0;
+    const int iend = x.isY ? m.sp_off[x.k + 1] : 0;
+    for (int j0 = 0; j0 < R; j0 += CH) {
+        const int j1 = min(R, j0 + CH);
+        for (int j = j0 + r; j < j1; j += G) {
+            const RxEval e = eval_reaction(m, L, j, x.T, x.lnT, x.invT, x.lnPRT, false);
+            double q = e.kf * e.Pf - e.kr * e.Pp;
+            if (e.kind == 1) q *= e.Mc;
+            L.rec[j - j0] = q;
         }
-    const double hw = gsum(x.isY ? th.h * wdot : 0.0);
-    const double cpm = gsum(x.isY ? x.Y * th.cp * x.invW : 0.0);
+        sync_wave();
+        for (; i < iend; ++i) {
+            const int2 e = m.sp_rx[i];
+            if (e.x >= j1) break;
+            wdot += e.y * L.rec[e.x - j0];
+        }
+        sync_wave();
+    }
+    const double hw = gsum<G>(x.isY ? th.h * wdot : 0.0);
+    const double cpm = gsum<G>(x.isY ? x.Y * th.cp * x.invW : 0.0);
     if (r == 0) return -hw * x.T / (x.rho * cpm);
     return x.isY ? m.W[x.k] * wdot / x.rho : 0.0;
 }
 
-// Jacobian into L.J (row-major 16 x 16, rows/cols beyond N untouched = 0)
-__device__ void jac_g(const DevMech &m, const GL &L, int r, double yv, double P) {
-    const int K = m.K;
+// Jacobian into L.J (row-major NC x (NC + 1); rows/columns beyond N are 0)
+template <int G, int NC>
+__device__ __forceinline__ void jac_g(const DevMech &m, const GL &L, int r, double yv, double P) {
+    constexpr int LD = NC + 1;
+    const int K = m.K, R = m.R, CH = rec_chunk(R);
     Thermo th;
-    const Mix x = mixture(m, L, r, yv, P, th);
+    const Mix x = mixture<G>(m, L, r, yv, P, th);
     const double T = x.T, invT = x.invT, rho = x.rho, Wbar = x.Wbar;
-    for (int i = r; i < G * G; i += G) L.J[i] = 0.0;
-    // per-reaction records: q, dq/dT|C, S, dense coefficient, 4 mass-action partials
-    for (int j = r; j < m.R; j += G) {
-        const RxEval e = eval_reaction(m, L, j, T, x.lnT, invT, x.lnPRT, true);
-        const double Rj = e.kf * e.Pf - e.kr * e.Pp;
-        const double dRdT = Rj * e.dlnkf + e.kr * e.Pp * e.dlnKc;
-        const double sMA = e.kind == 1 ? e.Mc : 1.0;
-        const double ctb = e.kind == 1 ? Rj : (e.kind == 2 ? Rj * e.dlnkf_dM : 0.0);
-        const int4 sp = e.sp;
-        const double Cr0 = L.C[sp.x], Cr1 = sp.y >= 0 ? L.C[sp.y] : 1.0;
-        const double Cp0 = L.C[sp.z], Cp1 = sp.w >= 0 ? L.C[sp.w] : 1.0;
-        double *rc = L.rec + 8 * j;
-        rc[0] = sMA * Rj;
-        rc[1] = sMA * dRdT;
-        rc[2] = sMA * (e.nr * e.kf * e.Pf - e.np * e.kr * e.Pp) + ctb * e.Mc;
-        rc[3] = ctb;
-        rc[4] = sMA * e.kf * Cr1;
-        rc[5] = sMA * e.kf * Cr0;
-        rc[6] = -sMA * e.kr * Cp1;
-        rc[7] = -sMA * e.kr * Cp0;
-    }
-    sync_wave();
-    // Mkm = sum_j nu_kj dq_j/dC_m into the Y block; lane r owns column r (species r-1)
-    if (x.isY) {
-        const int mm = x.k;
-        for (int j = 0; j < m.R; ++j) {
-            const int4 sp = m.rsp[j];
-            const int info = m.rinfo[j];
-            const double *rc = L.rec + 8 * j;
-            double dq = 0.0;
-            if (mm == sp.x) dq += rc[4];
-            if (mm == sp.y) dq += rc[5];
-            if (mm == sp.z) dq += rc[6];
-            if (mm == sp.w) dq += rc[7];
-            if (info & 15) dq += rc[3] * m.eff[(size_t)((info >> 12) - 1) * K + mm];
-            if (dq != 0.0) {
-                L.J[(1 + sp.x) * G + r] -= dq;
-                if (sp.y >= 0) L.J[(1 + sp.y) * G + r] -= dq;
-                L.J[(1 + sp.z) * G + r] += dq;
-                if (sp.w >= 0) L.J[(1 + sp.w) * G + r] += dq;
+    for (int i = r; i < NC * LD; i += G) L.J[i] = 0.0;
+    double wdot = 0.0, dwdT = 0.0, sS = 0.0;
+    int i = x.isY ? m.sp_off[x.k] : 0;
+    const int iend = x.isY ? m.sp_off[x.k + 1] : 0;
+    for (int j0 = 0; j0 < R; j0 += CH) {
+        const int j1 = min(R, j0 + CH);
+        // per-reaction records: q, dq/dT|C, S, dense coefficient, 4 mass-action partials
+        for (int j = j0 + r; j < j1; j += G) {
+            const RxEval e = eval_reaction(m, L, j, T, x.lnT, invT, x.lnPRT, true);
+            const double Rj = e.kf * e.Pf - e.kr * e.Pp;
+            const double dRdT = Rj * e.dlnkf + e.kr * e.Pp * e.dlnKc;
+            const double sMA = e.kind == 1 ? e.Mc : 1.0;
+            const double ctb = e.kind == 1 ? Rj : (e.kind == 2 ? Rj * e.dlnkf_dM : 0.0);
+            const int4 sp = e.sp;
+            const double Cr0 = L.C[sp.x], Cr1 = sp.y >= 0 ? L.C[sp.y] : 1.0;
+            const double Cp0 = L.C[sp.z], Cp1 = sp.w >= 0 ? L.C[sp.w] : 1.0;
+            double *rc = L.rec + 8 * (j - j0);
+            rc[0] = sMA * Rj;
+            rc[1] = sMA * dRdT;
+            rc[2] = sMA * (e.nr * e.kf * e.Pf - e.np * e.kr * e.Pp) + ctb * e.Mc;
+            rc[3] = ctb;
+            rc[4] = sMA * e.kf * Cr1;
+            rc[5] = sMA * e.kf * Cr0;
+            rc[6] = -sMA * e.kr * Cp1;
+            rc[7] = -sMA * e.kr * Cp0;
+        }
+        sync_wave();
+        // Mkm = sum_j nu_kj dq_j/dC_m into the Y block; lane r owns column r (species r-1)
+        if (x.isY) {
+            const int mm = x.k;
+            for (int j = j0; j < j1; ++j) {
+                const int4 sp = m.rsp[j];
+                const int info = m.rinfo[j];
+                const double *rc = L.rec + 8 * (j - j0);
+                double dq = 0.0;
+                if (mm == sp.x) dq += rc[4];
+                if (mm == sp.y) dq += rc[5];
+                if (mm == sp.z) dq += rc[6];
+                if (mm == sp.w) dq += rc[7];
+                if (info & 15) dq += rc[3] * m.eff[(size_t)((info >> 12) - 1) * K + mm];
+                if (dq != 0.0) {
+                    L.J[(1 + sp.x) * LD + r] -= dq;
+                    if (sp.y >= 0) L.J[(1 + sp.y) * LD + r] -= dq;
+                    L.J[(1 + sp.z) * LD + r] += dq;
+                    if (sp.w >= 0) L.J[(1 + sp.w) * LD + r] += dq;
+                }
             }
         }
-    }
-    // species sums
-    double wdot = 0.0, dwdT = 0.0, sS = 0.0;
-    if (x.isY)
-        for (int i = m.sp_off[x.k]; i < m.sp_off[x.k + 1]; ++i) {
+        // species sums over this chunk, in reaction order
+        for (; i < iend; ++i) {
             const int2 e = m.sp_rx[i];
-            const double *rc = L.rec + 8 * e.x;
+            if (e.x >= j1) break;
+            const double *rc = L.rec + 8 * (e.x - j0);
             wdot += e.y * rc[0];
             dwdT += e.y * rc[1];
             sS += e.y * rc[2];
         }
-    sync_wave();
+        sync_wave();
+    }
     // temperature row (lane r: column r)
     const double hk = th.h * T;
-    const double cpmix = gsum(x.Y * th.cp * x.invW);
-    const double dcpmix = gsum(x.Y * th.dcp * x.invW);
-    const double hw = gsum(x.isY ? hk * wdot : 0.0);
-    const double dHdT = gsum(x.isY ? th.cp * wdot + hk * (dwdT - sS * invT) : 0.0);
-    const double hsS = gsum(x.isY ? hk * sS : 0.0);
+    const double cpmix = gsum<G>(x.Y * th.cp * x.invW);
+    const double dcpmix = gsum<G>(x.Y * th.dcp * x.invW);
+    const double hw = gsum<G>(x.isY ? hk * wdot : 0.0);
+    const double dHdT = gsum<G>(x.isY ? th.cp * wdot + hk * (dwdT - sS * invT) : 0.0);
+    const double hsS = gsum<G>(x.isY ? hk * sS : 0.0);
     const double rcp = rho * cpmix;
     const double fT = -hw / rcp;
     if (x.isY) {
         double hM = 0.0;
-        for (int k = 0; k < K; ++k) hM += L.h[k] * T * L.J[(1 + k) * G + r];
+        for (int k = 0; k < K; ++k) hM += L.h[k] * T * L.J[(1 + k) * LD + r];
         const double dHdY = (rho * hM - Wbar * hsS) * x.invW;
         L.J[r] = -dHdY / rcp - fT * (th.cp * x.invW / cpmix - Wbar * x.invW);
     }
@@ -320,7 +372,7 @@ __device__ void jac_g(const DevMech &m, const GL &L, int r, double yv, double P)
         const double Wk = m.W[x.k];
         const double fk = Wk * wdot / rho;
         const double a = Wbar * (fk - Wk * sS / rho);
-        double *row = L.J + r * G;
+        double *row = L.J + r * LD;
         row[0] = Wk / rho * (dwdT - sS * invT) + fk * invT;
         for (int c = 1; c <= K; ++c) row[c] = (Wk * row[c] + a) * m.invW[c - 1];
     }
@@ -330,184 +382,229 @@ __device__ void jac_g(const DevMech &m, const GL &L, int r, double yv, double P)
 // ---------------------------------------------------------------------------
 // LU with partial pivoting by row ownership, then rows moved to pivot order.
 // Step k picks, among the rows not yet used, the one with the largest
-// magnitude in column k; its lane broadcasts the row through LDS and the
-// remaining rows are eliminated (every register index is a compile-time
-// constant).  Afterwards the rows are permuted so that lane k holds row k of
-// L\U (P E = L U), which lets the substitutions broadcast from lane k with an
-// in-row DPP move.
+// magnitude in column k; its lane broadcasts the row (through LDS for G = 16,
+// where the four groups of a wavefront pivot on different lanes, with
+// readlane for G = 64) and the remaining rows are eliminated (every register
+// index is a compile-time constant).  Afterwards the rows are permuted so
+// that lane k holds row k of L\U (P E = L U), which lets the substitutions
+// broadcast from lane k with a constant lane index.
 // ---------------------------------------------------------------------------
 // S is the storage (and elimination) precision of the factors: double for
 // the plain path, float for the mixed path.  Substitutions run in double.
 // With float factors the matrix is equilibrated first: columns scaled by the
 // error weights sc_c (a similarity with rows 1/sc_r) and rows by their
 // largest entry; rs = row factor of the lane's row, cs = sc of its column.
-template <typename S>
+template <typename S, int NC>
 struct LUR {
-    S a[G];
+    S a[NC];
     double dinv;      // 1 / U_kk of the lane's row
-    uint64_t perm;    // pivot lane of step k in bits 4k..4k+3
+    int src;          // lane whose row became pivot at step r (the lane's own r beyond N)
     double rs, cs;
 };
 
-template <typename S>
+template <typename S, int NC>
 struct LUC {
-    S re[G], im[G];
+    S re[NC], im[NC];
     double dr, di;    // 1 / U_kk
-    uint64_t perm;
+    int src;
     double rs, cs;
 };
 
-// value of lane k of the 16-lane row (row_newbcast:k); k is a constant once the
-// calling loops are unrolled, so the switch folds away
+// value of lane k of the group; k is a constant once the calling loops are
+// unrolled (row_newbcast:k DPP within a 16-lane row, readlane for G = 64)
+template <int G>
 __device__ __forceinline__ double bcast(double v, int k) {
-    switch (k) {
-        case 0: return dpp<0x150>(v);
-        case 1: return dpp<0x151>(v);
-        case 2: return dpp<0x152>(v);
-        case 3: return dpp<0x153>(v);
-        case 4: return dpp<0x154>(v);
-        case 5: return dpp<0x155>(v);
-        case 6: return dpp<0x156>(v);
-        case 7: return dpp<0x157>(v);
-        case 8: return dpp<0x158>(v);
-        case 9: return dpp<0x159>(v);
-        case 10: return dpp<0x15A>(v);
-        case 11: return dpp<0x15B>(v);
-        case 12: return dpp<0x15C>(v);
-        case 13: return dpp<0x15D>(v);
-        case 14: return dpp<0x15E>(v);
-        default: return dpp<0x15F>(v);
+    if constexpr (G == 64) {
+        return rlane(v, k);
+    } else {
+        switch (k) {
+            case 0: return dpp<0x150>(v);
+            case 1: return dpp<0x151>(v);
+            case 2: return dpp<0x152>(v);
+            case 3: return dpp<0x153>(v);
+            case 4: return dpp<0x154>(v);
+            case 5: return dpp<0x155>(v);
+            case 6: return dpp<0x156>(v);
+            case 7: return dpp<0x157>(v);
+            case 8: return dpp<0x158>(v);
+            case 9: return dpp<0x159>(v);
+            case 10: return dpp<0x15A>(v);
+            case 11: return dpp<0x15B>(v);
+            case 12: return dpp<0x15C>(v);
+            case 13: return dpp<0x15D>(v);
+            case 14: return dpp<0x15E>(v);
+            default: return dpp<0x15F>(v);
+        }
     }
 }
 
-__device__ __forceinline__ int perm_at(uint64_t perm, int k) { return (int)((perm >> (4 * k)) & 15); }
-
-template <typename S>
-__device__ void factor_real(LUR<S> &F, const GL &L, int r, int N) {
+template <typename S, int G, int NC>
+__device__ __forceinline__ void factor_real(LUR<S, NC> &F, const GL &L, int r, int N) {
     bool used = r >= N;
-    F.perm = 0;
+    int src = r;
     double dinv = 0.0;
 #pragma unroll
-    for (int k = 0; k < G; ++k) {
+    for (int k = 0; k < NC; ++k) {
         if (k < N) {
-            const int p = gpivot(fabs((double)F.a[k]), used, r);
-            F.perm |= (uint64_t)p << (4 * k);
-            if (r == p) {
-                used = true;
-                dinv = 1.0 / (double)F.a[k];
+            const int p = gpivot<G>(fabs((double)F.a[k]), used, r);
+            if (r == k) src = p;
+            if constexpr (G == 64) {
+                if (r == p) {
+                    used = true;
+                    dinv = 1.0 / (double)F.a[k];
+                }
+                const S pk = rlane(F.a[k], p);
+                const S l = F.a[k] / pk;
+                if (!used) F.a[k] = l;
 #pragma unroll
-                for (int c = k; c < G; ++c) L.prow[c] = (double)F.a[c];
-            }
-            sync_wave();
-            if (!used) {
-                const S l = F.a[k] / (S)L.prow[k];
-                F.a[k] = l;
+                for (int c = k + 1; c < NC; ++c) {
+                    const S pc = rlane(F.a[c], p);
+                    if (!used) F.a[c] -= l * pc;
+                }
+            } else {
+                if (r == p) {
+                    used = true;
+                    dinv = 1.0 / (double)F.a[k];
 #pragma unroll
-                for (int c = k + 1; c < G; ++c) F.a[c] -= l * (S)L.prow[c];
+                    for (int c = k; c < NC; ++c) L.prow[c] = (double)F.a[c];
+                }
+                sync_wave();
+                if (!used) {
+                    const S l = F.a[k] / (S)L.prow[k];
+                    F.a[k] = l;
+#pragma unroll
+                    for (int c = k + 1; c < NC; ++c) F.a[c] -= l * (S)L.prow[c];
+                }
+                sync_wave();
             }
-            sync_wave();
         }
     }
     // lane k takes the row that became pivot at step k
-    const int src = r < N ? perm_at(F.perm, r) : r;
 #pragma unroll
-    for (int c = 0; c < G; ++c) F.a[c] = gb(F.a[c], src);
-    F.dinv = gb(dinv, src);
+    for (int c = 0; c < NC; ++c) F.a[c] = gb<G>(F.a[c], src);
+    F.dinv = gb<G>(dinv, src);
+    F.src = src;
 }
 
-template <typename S>
-__device__ void factor_cplx(LUC<S> &F, const GL &L, int r, int N) {
+template <typename S, int G, int NC>
+__device__ __forceinline__ void factor_cplx(LUC<S, NC> &F, const GL &L, int r, int N) {
     bool used = r >= N;
-    F.perm = 0;
+    int src = r;
     double dr = 0.0, di = 0.0;
 #pragma unroll
-    for (int k = 0; k < G; ++k) {
+    for (int k = 0; k < NC; ++k) {
         if (k < N) {
             const double mr = F.re[k], mi = F.im[k];
-            const int p = gpivot(mr * mr + mi * mi, used, r);
-            F.perm |= (uint64_t)p << (4 * k);
+            const int p = gpivot<G>(mr * mr + mi * mi, used, r);
+            if (r == k) src = p;
             if (r == p) {
                 used = true;
                 const double dd = 1.0 / (mr * mr + mi * mi);
                 dr = mr * dd;
                 di = -mi * dd;
+                if constexpr (G != 64) {
 #pragma unroll
-                for (int c = k; c < G; ++c) { L.prow[c] = (double)F.re[c]; L.prow[G + c] = (double)F.im[c]; }
+                    for (int c = k; c < NC; ++c) { L.prow[c] = (double)F.re[c]; L.prow[NC + c] = (double)F.im[c]; }
+                }
             }
-            sync_wave();
+            S pr, pi;
+            if constexpr (G == 64) {
+                pr = rlane(F.re[k], p);
+                pi = rlane(F.im[k], p);
+            } else {
+                sync_wave();
+                pr = (S)L.prow[k];
+                pi = (S)L.prow[NC + k];
+            }
+            const S dd = (S)1 / (pr * pr + pi * pi);
+            const S ir = pr * dd, ii = -pi * dd;
+            const S xr = F.re[k], xi = F.im[k];
+            const S lr = xr * ir - xi * ii, li = xr * ii + xi * ir;
             if (!used) {
-                const S pr = (S)L.prow[k], pi = (S)L.prow[G + k];
-                const S dd = (S)1 / (pr * pr + pi * pi);
-                const S ir = pr * dd, ii = -pi * dd;
-                const S xr = F.re[k], xi = F.im[k];
-                const S lr = xr * ir - xi * ii, li = xr * ii + xi * ir;
                 F.re[k] = lr;
                 F.im[k] = li;
+            }
 #pragma unroll
-                for (int c = k + 1; c < G; ++c) {
-                    const S ur = (S)L.prow[c], ui = (S)L.prow[G + c];
+            for (int c = k + 1; c < NC; ++c) {
+                S ur, ui;
+                if constexpr (G == 64) {
+                    ur = rlane(F.re[c], p);
+                    ui = rlane(F.im[c], p);
+                } else {
+                    ur = (S)L.prow[c];
+                    ui = (S)L.prow[NC + c];
+                }
+                if (!used) {
                     F.re[c] -= lr * ur - li * ui;
                     F.im[c] -= lr * ui + li * ur;
                 }
             }
-            sync_wave();
+            if constexpr (G != 64) sync_wave();
         }
     }
-    const int src = r < N ? perm_at(F.perm, r) : r;
 #pragma unroll
-    for (int c = 0; c < G; ++c) {
-        F.re[c] = gb(F.re[c], src);
-        F.im[c] = gb(F.im[c], src);
+    for (int c = 0; c < NC; ++c) {
+        F.re[c] = gb<G>(F.re[c], src);
+        F.im[c] = gb<G>(F.im[c], src);
     }
-    F.dr = gb(dr, src);
-    F.di = gb(di, src);
+    F.dr = gb<G>(dr, src);
+    F.di = gb<G>(di, src);
+    F.src = src;
+}
+
+// factor entry widened to double at its point of use: the empty asm keeps the
+// compiler from hoisting the conversions of all entries out of the Newton loop
+// (which would hold a double copy of both factorisations in registers)
+__device__ __forceinline__ double wide(double v) { return v; }
+__device__ __forceinline__ double wide(float v) {
+    asm volatile("" : "+v"(v));
+    return (double)v;
 }
 
 // x = E^-1 b, component r in lane r in and out
-template <typename S>
-__device__ double solve_real(const LUR<S> &F, int r, int N, double b) {
-    double acc = gb(b * F.rs, r < N ? perm_at(F.perm, r) : r);        // P b (equilibrated)
+template <typename S, int G, int NC>
+__device__ __forceinline__ double solve_real(const LUR<S, NC> &F, int r, int N, double b) {
+    double acc = gb<G>(b * F.rs, F.src);        // P b (equilibrated)
 #pragma unroll
-    for (int k = 0; k < G; ++k)
+    for (int k = 0; k < NC; ++k)
         if (k < N) {
-            const double yk = bcast(acc, k);
-            if (r > k) acc -= (double)F.a[k] * yk;
+            const double yk = bcast<G>(acc, k);
+            if (r > k) acc -= wide(F.a[k]) * yk;
         }
 #pragma unroll
-    for (int k = G - 1; k >= 0; --k)
+    for (int k = NC - 1; k >= 0; --k)
         if (k < N) {
             if (r == k) acc *= F.dinv;
-            const double xk = bcast(acc, k);
-            if (r < k) acc -= (double)F.a[k] * xk;
+            const double xk = bcast<G>(acc, k);
+            if (r < k) acc -= wide(F.a[k]) * xk;
         }
     return r < N ? acc * F.cs : 0.0;
 }
 
-template <typename S>
-__device__ void solve_cplx(const LUC<S> &F, int r, int N, double &br, double &bi) {
-    const int src = r < N ? perm_at(F.perm, r) : r;
-    double ar = gb(br * F.rs, src), ai = gb(bi * F.rs, src);
+template <typename S, int G, int NC>
+__device__ __forceinline__ void solve_cplx(const LUC<S, NC> &F, int r, int N, double &br, double &bi) {
+    double ar = gb<G>(br * F.rs, F.src), ai = gb<G>(bi * F.rs, F.src);
 #pragma unroll
-    for (int k = 0; k < G; ++k)
+    for (int k = 0; k < NC; ++k)
         if (k < N) {
-            const double yr = bcast(ar, k), yi = bcast(ai, k);
+            const double yr = bcast<G>(ar, k), yi = bcast<G>(ai, k);
             if (r > k) {
-                const double lr = F.re[k], li = F.im[k];
+                const double lr = wide(F.re[k]), li = wide(F.im[k]);
                 ar -= lr * yr - li * yi;
                 ai -= lr * yi + li * yr;
             }
         }
 #pragma unroll
-    for (int k = G - 1; k >= 0; --k)
+    for (int k = NC - 1; k >= 0; --k)
         if (k < N) {
             if (r == k) {
                 const double tr = ar * F.dr - ai * F.di;
                 ai = ar * F.di + ai * F.dr;
                 ar = tr;
             }
-            const double xr = bcast(ar, k), xi = bcast(ai, k);
+            const double xr = bcast<G>(ar, k), xi = bcast<G>(ai, k);
             if (r < k) {
-                const double ur = F.re[k], ui = F.im[k];
+                const double ur = wide(F.re[k]), ui = wide(F.im[k]);
                 ar -= ur * xr - ui * xi;
                 ai -= ur * xi + ui * xr;
             }
@@ -518,14 +615,15 @@ __device__ void solve_cplx(const LUC<S> &F, int r, int N, double &br, double &bi
 
 // FP64 product of the iteration matrix c I - J (J row-major in LDS) with x
 // (component r in lane r), used for residuals of the mixed-precision solves
-__device__ double ematvec(const GL &L, int r, int N, double c, double x) {
+template <int NC>
+__device__ __forceinline__ double ematvec(const GL &L, int r, int N, double c, double x) {
     sync_wave();
-    L.vx[r] = x;
+    if (r < NC) L.vx[r] = x;
     sync_wave();
     double acc = c * x;
-    const double *row = L.J + r * G;
+    const double *row = L.J + (r < NC ? r : 0) * (NC + 1);
 #pragma unroll
-    for (int k = 0; k < G; ++k)
+    for (int k = 0; k < NC; ++k)
         if (k < N) acc -= row[k] * L.vx[k];
     sync_wave();
     return r < N ? acc : 0.0;
@@ -550,7 +648,7 @@ __global__ void collect_fallback_kernel(const int32_t *__restrict__ cnt, int64_t
 // takes the next state from the queue in the next iteration without waiting
 // for the other groups of its wavefront.  The wavefront leaves the loop when
 // no group holds a state.
-template <typename S>
+template <typename S, int G, int NC>
 __global__ __launch_bounds__(64) void radau_group_kernel(DevMech m, RadauParams rp, int64_t n,
                                                          const double *__restrict__ yin, double *__restrict__ yout,
                                                          int32_t *__restrict__ cnt, int *__restrict__ queue,
@@ -562,14 +660,14 @@ __global__ __launch_bounds__(64) void radau_group_kernel(DevMech m, RadauParams 
     const int r = threadIdx.x & (G - 1);
     const int grp = threadIdx.x / G;
     const int N = m.N, K = m.K;
-    const GL L = group_lds(smem + (size_t)grp * group_lds_doubles(m.R), m.R);
+    const GL L = group_lds<NC>(smem + (size_t)grp * group_lds_doubles(NC, m.R), m.R);
     const bool comp = r < N;                       // lane holds a state component
     const double dt = rp.dt, atol = rp.atol, rtol = rp.rtol, kappa = rp.kappa;
     const int kmax = rp.kmax;
 
     const int64_t nwork = work_n ? (int64_t)*work_n : n;
-    LUR<S> E1;
-    LUC<S> E2;
+    LUR<S, NC> E1;
+    LUC<S, NC> E2;
     int ndiv_row = 0;      // consecutive Newton divergences since the last accepted step
     bool warm = false;     // first attempt starts from the predictor
     int flags = 0;
@@ -589,7 +687,7 @@ __global__ __launch_bounds__(64) void radau_group_kernel(DevMech m, RadauParams 
         if (!have && !drained) {
             int qi = 0;
             if (r == 0) qi = atomicAdd(queue, 1);
-            qi = gbi(qi, 0);
+            qi = gbi<G>(qi, 0);
             if (qi >= nwork) {
                 drained = true;
             } else {
@@ -599,7 +697,7 @@ __global__ __launch_bounds__(64) void radau_group_kernel(DevMech m, RadauParams 
                 const bool bad_l = (comp && !isfinite(y)) || (r == 0 && !(y > 0.0)) ||
                                    (r == 0 && !(P > 0.0 && isfinite(P)));
                 nstep = nacc = nrej = nnewt = nnf = nfev = njev = nlu = 0;
-                if (gsum(bad_l ? 1.0 : 0.0) > 0.0) {
+                if (gsum<G>(bad_l ? 1.0 : 0.0) > 0.0) {
                     status = RK_ST_NONFINITE;
                     if (comp) yout[(size_t)r * n + s] = y;
                     if (r == 0) yout[(size_t)(K + 1) * n + s] = P;
@@ -613,19 +711,20 @@ __global__ __launch_bounds__(64) void radau_group_kernel(DevMech m, RadauParams 
                     flags = 0;
                     t = 0.0;
                     warm = pred != nullptr;
+                    h = rp.h0;
                     if (warm) {
+                        // warm start: predicted first step (0: the default rule) and stage values
                         const double *ps = pred + (size_t)s * PD;
                         const bool zuse = (rp.pred_use & 2) != 0;
-                        h = (rp.pred_use & 1) ? ps[3 * N] : rp.h0;
+                        if ((rp.pred_use & 1) && ps[3 * N] > 0.0) h = ps[3 * N];
                         Zw1 = comp && zuse ? ps[r] : 0.0;
                         Zw2 = comp && zuse ? ps[N + r] : 0.0;
                         Zw3 = comp && zuse ? ps[2 * N + r] : 0.0;
-                        warm = h > 0.0 && rp.pred_use != 0;
+                        warm = rp.pred_use != 0;
                     }
-                    if (!warm) h = rp.h0;
                     last = false;
                     if (t + 1.0001 * h >= dt) { h = dt - t; last = true; }
-                    f0 = rhs_g(m, L, r, y, P);
+                    f0 = rhs_g<G>(m, L, r, y, P);
                     nfev = 1;
                     sc = comp ? atol + rtol * fabs(y) : 1.0;
                     first = true;
@@ -647,38 +746,39 @@ __global__ __launch_bounds__(64) void radau_group_kernel(DevMech m, RadauParams 
 
         // ---- one step attempt ---------------------------------------------------
         if (action == ACT_JAC) {
-            jac_g(m, L, r, y, P);
+            jac_g<G, NC>(m, L, r, y, P);
             ++njev;
             jac_fresh = true;
             action = ACT_LU;
         }
         if (action == ACT_LU) {
             const double gh = rp.g / h, ah = rp.a / h, bh = rp.b / h;
-            const double *row = L.J + r * G;
+            const double *row = L.J + (r < NC ? r : 0) * (NC + 1);
             if constexpr (kMixed) {
-                // equilibrate: E'' = diag(1/(sc_r m_r)) E diag(sc_c)
-                sync_wave();
-                L.vx[r] = comp ? sc : 1.0;
-                sync_wave();
-                double e1[G], e2r[G];
+                // equilibrate: E'' = diag(1/(sc_r m_r)) E diag(sc_c).  The column
+                // scaling is applied in FP64 before rounding, the row factor m_r (the
+                // power of two at or below the row maximum, so exact) afterwards
+                const double scv = comp ? sc : 1.0;
                 double m1 = 0.0, m2 = 0.0;
-                const double isc = 1.0 / (comp ? sc : 1.0);
+                const double isc = 1.0 / scv;
 #pragma unroll
-                for (int c = 0; c < G; ++c) {
+                for (int c = 0; c < NC; ++c) {
                     const double j = comp ? row[c] : 0.0;
-                    const double w = L.vx[c] * isc;
-                    e1[c] = ((c == r ? gh : 0.0) - j) * w;
-                    e2r[c] = ((c == r ? ah : 0.0) - j) * w;
-                    m1 = fmax(m1, fabs(e1[c]));
-                    m2 = fmax(m2, fabs(e2r[c]));
+                    const double w = bcast<G>(scv, c) * isc;
+                    const double v1 = ((c == r ? gh : 0.0) - j) * w, v2 = ((c == r ? ah : 0.0) - j) * w;
+                    m1 = fmax(m1, fabs(v1));
+                    m2 = fmax(m2, fabs(v2));
+                    E1.a[c] = (S)v1;
+                    E2.re[c] = (S)v2;
                 }
                 const double e2i = bh;      // imaginary part: diagonal only, scale w = 1
                 m2 = fmax(m2, e2i);
-                const double i1 = 1.0 / m1, i2 = 1.0 / m2;
+                const double i1 = 1.0 / exp2(floor(log2(m1))), i2 = 1.0 / exp2(floor(log2(m2)));
+                const S f1 = (S)i1, f2 = (S)i2;
 #pragma unroll
-                for (int c = 0; c < G; ++c) {
-                    E1.a[c] = (S)(e1[c] * i1);
-                    E2.re[c] = (S)(e2r[c] * i2);
+                for (int c = 0; c < NC; ++c) {
+                    E1.a[c] *= f1;
+                    E2.re[c] *= f2;
                     E2.im[c] = (S)(c == r ? e2i * i2 : 0.0);
                 }
                 E1.rs = isc * i1;
@@ -687,21 +787,21 @@ __global__ __launch_bounds__(64) void radau_group_kernel(DevMech m, RadauParams 
                 sync_wave();
             } else {
 #pragma unroll
-                for (int c = 0; c < G; ++c) {
+                for (int c = 0; c < NC; ++c) {
                     const double j = comp ? row[c] : 0.0;
                     E1.a[c] = -j;
                     E2.re[c] = -j;
                     E2.im[c] = 0.0;
                 }
 #pragma unroll
-                for (int c = 0; c < G; ++c)
+                for (int c = 0; c < NC; ++c)
                     if (c == r) { E1.a[c] += gh; E2.re[c] += ah; E2.im[c] = bh; }
                 E1.rs = E2.rs = 1.0;
                 E1.cs = E2.cs = 1.0;
                 sync_wave();
             }
-            factor_real(E1, L, r, N);
-            factor_cplx(E2, L, r, N);
+            factor_real<S, G>(E1, L, r, N);
+            factor_cplx<S, G>(E2, L, r, N);
             ++nlu;
         }
         action = ACT_SAME;
@@ -739,9 +839,9 @@ __global__ __launch_bounds__(64) void radau_group_kernel(DevMech m, RadauParams 
             int newt = 0;
             double dn_old = 1.0;
             for (int it = 1; it <= kmax; ++it) {
-                const double F1 = rhs_g(m, L, r, y + Z1, P);
-                const double F2 = rhs_g(m, L, r, y + Z2, P);
-                const double F3 = rhs_g(m, L, r, y + Z3, P);
+                const double F1 = rhs_g<G>(m, L, r, y + Z1, P);
+                const double F2 = rhs_g<G>(m, L, r, y + Z2, P);
+                const double F3 = rhs_g<G>(m, L, r, y + Z3, P);
                 nfev += 3;
                 const double gh = rp.g / h, ah = rp.a / h, bh = rp.b / h;
                 const double G1 = rp.Ti[0] * F1 + rp.Ti[1] * F2 + rp.Ti[2] * F3;
@@ -750,15 +850,15 @@ __global__ __launch_bounds__(64) void radau_group_kernel(DevMech m, RadauParams 
                 const double b1 = comp ? G1 - gh * W1 : 0.0;
                 const double b2 = comp ? G2 - (ah * W2 - bh * W3) : 0.0;
                 const double b3 = comp ? G3 - (bh * W2 + ah * W3) : 0.0;
-                double dW1 = solve_real(E1, r, N, b1);
+                double dW1 = solve_real<S, G>(E1, r, N, b1);
                 double dW2 = b2, dW3 = b3;
-                solve_cplx(E2, r, N, dW2, dW3);
+                solve_cplx<S, G>(E2, r, N, dW2, dW3);
                 if constexpr (kMixed) {
                     // one refinement step against the FP64 matrices
-                    dW1 += solve_real(E1, r, N, b1 - ematvec(L, r, N, gh, dW1));
-                    double q2 = b2 - (ematvec(L, r, N, ah, dW2) - bh * dW3);
-                    double q3 = b3 - (ematvec(L, r, N, ah, dW3) + bh * dW2);
-                    solve_cplx(E2, r, N, q2, q3);
+                    dW1 += solve_real<S, G>(E1, r, N, b1 - ematvec<NC>(L, r, N, gh, dW1));
+                    double q2 = b2 - (ematvec<NC>(L, r, N, ah, dW2) - bh * dW3);
+                    double q3 = b3 - (ematvec<NC>(L, r, N, ah, dW3) + bh * dW2);
+                    solve_cplx<S, G>(E2, r, N, q2, q3);
                     dW2 += q2;
                     dW3 += q3;
                 }
@@ -767,7 +867,7 @@ __global__ __launch_bounds__(64) void radau_group_kernel(DevMech m, RadauParams 
                 const double dZ3 = rp.T[6] * dW1 + rp.T[7] * dW2 + rp.T[8] * dW3;
                 ++nnewt;
                 newt = it;
-                const double dn = sqrt(gsum(comp ? (dZ1 * dZ1 + dZ2 * dZ2 + dZ3 * dZ3) / (sc * sc) : 0.0) / (3 * N));
+                const double dn = sqrt(gsum<G>(comp ? (dZ1 * dZ1 + dZ2 * dZ2 + dZ3 * dZ3) / (sc * sc) : 0.0) / (3 * N));
                 if (!isfinite(dn)) { diverged = true; break; }
                 if (it >= 2) {
                     const double th = dn / dn_old;
@@ -782,14 +882,18 @@ __global__ __launch_bounds__(64) void radau_group_kernel(DevMech m, RadauParams 
                 if (eta * dn <= kappa) { converged = true; break; }
             }
             if (!converged && warm) {
-                // the prediction did not converge: start the state cold
+                // the prediction did not converge: restart the state exactly as a cold
+                // start (default first step, zero starting values, controller memory)
                 ++nnf;
                 warm = false;
                 flags |= kFlagPredFallback;
                 h = rp.h0;
                 last = false;
                 if (t + 1.0001 * h >= dt) { h = dt - t; last = true; }
+                eta = 1.0;
+                theta = 1.0;
                 hacc = h;
+                erracc = 1e-2;
                 hlast = h;
                 action = ACT_LU;
             } else if (!converged) {
@@ -811,16 +915,16 @@ __global__ __launch_bounds__(64) void radau_group_kernel(DevMech m, RadauParams 
                 const double sc2 = comp ? atol + rtol * fmax(fabs(y), fabs(y + Z3)) : 1.0;
                 const double gh = rp.g / h;
                 double v = comp ? f0 + dz : 0.0;
-                double ev = solve_real(E1, r, N, v);
-                if constexpr (kMixed) ev += solve_real(E1, r, N, v - ematvec(L, r, N, gh, ev));   // FP64 residual
-                double err = fmax(sqrt(gsum(comp ? (ev / sc2) * (ev / sc2) : 0.0) / N), 1e-10);
+                double ev = solve_real<S, G>(E1, r, N, v);
+                if constexpr (kMixed) ev += solve_real<S, G>(E1, r, N, v - ematvec<NC>(L, r, N, gh, ev));   // FP64 residual
+                double err = fmax(sqrt(gsum<G>(comp ? (ev / sc2) * (ev / sc2) : 0.0) / N), 1e-10);
                 if (err >= 1.0 && (first || reject)) {
-                    const double fe = rhs_g(m, L, r, y + ev, P);
+                    const double fe = rhs_g<G>(m, L, r, y + ev, P);
                     ++nfev;
                     v = comp ? fe + dz : 0.0;
-                    ev = solve_real(E1, r, N, v);
-                    if constexpr (kMixed) ev += solve_real(E1, r, N, v - ematvec(L, r, N, gh, ev));
-                    err = fmax(sqrt(gsum(comp ? (ev / sc2) * (ev / sc2) : 0.0) / N), 1e-10);
+                    ev = solve_real<S, G>(E1, r, N, v);
+                    if constexpr (kMixed) ev += solve_real<S, G>(E1, r, N, v - ematvec<NC>(L, r, N, gh, ev));
+                    err = fmax(sqrt(gsum<G>(comp ? (ev / sc2) * (ev / sc2) : 0.0) / N), 1e-10);
                 }
                 if (!isfinite(err)) err = 1e300;
 
@@ -848,7 +952,7 @@ __global__ __launch_bounds__(64) void radau_group_kernel(DevMech m, RadauParams 
                     if (last) {
                         done = true;
                     } else {
-                        f0 = rhs_g(m, L, r, y, P);
+                        f0 = rhs_g<G>(m, L, r, y, P);
                         ++nfev;
                         if (reject) hnew = fmin(hnew, h);
                         reject = false;
@@ -912,36 +1016,79 @@ hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t st) {
     return hipGetLastError();
 }
 
-size_t group_lds_bytes(int R) { return (size_t)(kWave / G) * group_lds_doubles(R) * sizeof(double); }
+namespace {
+
+// launch shape per mechanism size: lanes per state and register columns
+struct GroupShape {
+    int G, NC;
+};
+
+GroupShape group_shape(int N) {
+    if (N <= 16) return {16, 16};
+    if (N <= 56) return {64, 56};
+    return {0, 0};
+}
+
+template <typename S, int G, int NC>
+void launch_one(const DevMech &m, const RadauParams &p, int64_t n, const double *yin, double *yout, int32_t *cnt,
+                int *queue, const int *order, const int *work_n, const double *pred, int grid, hipStream_t st) {
+    const size_t lds = (size_t)(kWave / G) * group_lds_doubles(NC, m.R) * sizeof(double);
+    hipLaunchKernelGGL((radau_group_kernel<S, G, NC>), dim3(grid), dim3(kWave), lds, st, m, p, n, yin, yout, cnt, queue,
+                       order, work_n, pred);
+}
+
+template <typename S>
+void launch_shape(const GroupShape &g, const DevMech &m, const RadauParams &p, int64_t n, const double *yin,
+                  double *yout, int32_t *cnt, int *queue, const int *order, const int *work_n, const double *pred,
+                  int grid, hipStream_t st) {
+    if (g.G == 16) launch_one<S, 16, 16>(m, p, n, yin, yout, cnt, queue, order, work_n, pred, grid, st);
+    else launch_one<S, 64, 56>(m, p, n, yin, yout, cnt, queue, order, work_n, pred, grid, st);
+}
+
+}  // namespace
+
+bool group_supported(int N) { return group_shape(N).G != 0; }
+
+int group_states_per_block(int N) {
+    const GroupShape g = group_shape(N);
+    return g.G ? kWave / g.G : 0;
+}
+
+size_t group_lds_bytes(int N, int R) {
+    const GroupShape g = group_shape(N);
+    if (!g.G) return 0;
+    return (size_t)(kWave / g.G) * group_lds_doubles(g.NC, R) * sizeof(double);
+}
 
 hipError_t launch_radau_group(const DevMech &m, const RadauParams &p, int64_t n, const double *yin, double *yout,
                               int32_t *counters, int *queue, int *fb_list, const int *order, const double *pred,
                               bool mixed, int grid, hipStream_t st) {
     if (n == 0) return hipSuccess;
-    if (m.N > G) return hipErrorInvalidValue;
+    const GroupShape g = group_shape(m.N);
+    if (!g.G) return hipErrorInvalidValue;
     hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, st, queue);
-    const size_t lds = group_lds_bytes(m.R);
     if (!mixed) {
-        hipLaunchKernelGGL(radau_group_kernel<double>, dim3(grid), dim3(kWave), lds, st, m, p, n, yin, yout, counters,
-                           queue, order, (const int *)nullptr, pred);
+        launch_shape<double>(g, m, p, n, yin, yout, counters, queue, order, nullptr, pred, grid, st);
         return hipGetLastError();
     }
     // mixed pass over every state, then an FP64 pass over the states it handed back
-    hipLaunchKernelGGL(radau_group_kernel<float>, dim3(grid), dim3(kWave), lds, st, m, p, n, yin, yout, counters,
-                       queue, order, (const int *)nullptr, pred);
+    launch_shape<float>(g, m, p, n, yin, yout, counters, queue, order, nullptr, pred, grid, st);
     hipLaunchKernelGGL(collect_fallback_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, counters, n,
                        fb_list, queue + 1);
     // the FP64 pass starts the handed-back states cold
-    hipLaunchKernelGGL(radau_group_kernel<double>, dim3(grid), dim3(kWave), lds, st, m, p, n, yin, yout, counters,
-                       queue + 2, (const int *)fb_list, (const int *)(queue + 1), (const double *)nullptr);
+    launch_shape<double>(g, m, p, n, yin, yout, counters, queue + 2, fb_list, queue + 1, nullptr, grid, st);
     return hipGetLastError();
 }
 
-int group_max_blocks(int R) {
+int group_max_blocks(int N, int R) {
+    const GroupShape g = group_shape(N);
+    if (!g.G) return 1;
+    const size_t lds = group_lds_bytes(N, R);
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, radau_group_kernel<double>, kWave, group_lds_bytes(R)) !=
-        hipSuccess)
-        per_cu = 1;
+    hipError_t e = g.G == 16
+        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, radau_group_kernel<double, 16, 16>, kWave, lds)
+        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, radau_group_kernel<double, 64, 56>, kWave, lds);
+    if (e != hipSuccess) per_cu = 1;
     int dev = 0, cus = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);

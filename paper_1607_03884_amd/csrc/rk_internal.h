@@ -75,13 +75,16 @@ size_t proxy_scratch_doubles(int K);
 hipError_t launch_binning(const DevMech &m, int64_t n, const double *yin, double dt, double atol, double rtol,
                           int nbins, int *bins, int *order, int *hist, double *scratch, hipStream_t st);
 size_t lane_scratch_doubles(int K, int64_t n);
-// group-cooperative variant (16 lanes per state, N <= 16), persistent work queue
+// group-cooperative variant (16 lanes per state for N <= 16, a wavefront per
+// state for N <= 56), persistent work queue
+bool group_supported(int N);
+int group_states_per_block(int N);
 hipError_t launch_radau_group(const DevMech &m, const RadauParams &p, int64_t n, const double *yin, double *yout,
                               int32_t *counters, int *queue, int *fb_list, const int *order, const double *pred,
                               bool mixed, int grid, hipStream_t st);
-int group_max_blocks(int R);
+int group_max_blocks(int N, int R);
 hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t st);
-size_t group_lds_bytes(int R);
+size_t group_lds_bytes(int N, int R);
 
 // Predictor network (rk_mlp.hip): FP32 masters, BF16 copy used in products.
 struct Mlp {

@@ -11,6 +11,7 @@ namespace rk {
 namespace {
 
 constexpr double kPatmF = 101325.0;
+constexpr double kLog2_10 = 3.321928094887362;    // log2(10)
 
 // X[s] = standardised [T / 1000, ln(P / 1 atm), Y_1..Y_K]
 __global__ void feature_kernel(int64_t n, int K, const double *__restrict__ yin, const float *__restrict__ shift,
@@ -27,8 +28,12 @@ __global__ void feature_kernel(int64_t n, int K, const double *__restrict__ yin,
     X[i] = (float)((f - (double)shift[j]) / (double)scale[j]);
 }
 
-// pred[s][0..3N) = first-step stage values z_ic, pred[s][3N] = first step size,
-// pred[s][3N+1] = predicted step attempts
+// pred[s][0..3N) = first-step stage values z_ic, pred[s][3N] = first step size
+// (0: the default rule), pred[s][3N+1] = predicted step attempts.
+// Stage values: t = symlog(z / sc) with sc = atol + rtol |y0|, |t| <= 40.
+// First step: t = log10(h / dt) in [-15, 0], rounded to the nearest power of
+// two times dt, h = dt 2^-q (exact), so that nearby predictions give the same
+// step.  A non-finite network output decodes to 0.
 __global__ void decode_kernel(int64_t n, int N, const float *__restrict__ Y, const float *__restrict__ shift,
                               const float *__restrict__ scale, const double *__restrict__ yin, double dt, double atol,
                               double rtol, double *__restrict__ pred) {
@@ -38,15 +43,18 @@ __global__ void decode_kernel(int64_t n, int N, const float *__restrict__ Y, con
     const int64_t s = i / D;
     const int j = (int)(i % D);
     double t = (double)Y[i] * (double)scale[j] + (double)shift[j];
-    double v;
-    if (j < 3 * N) {
+    double v = 0.0;
+    if (!isfinite(t)) {
+        v = 0.0;
+    } else if (j < 3 * N) {
         const int c = j % N;
         t = fmin(fmax(t, -40.0), 40.0);
         const double mag = expm1(fabs(t));
         const double sc = atol + rtol * fabs(yin[(size_t)c * n + s]);
         v = (t < 0.0 ? -mag : mag) * sc;
     } else if (j == 3 * N) {
-        v = dt * exp10(fmin(fmax(t, -15.0), 0.0));
+        const int q = (int)rint(-fmin(fmax(t, -15.0), 0.0) * kLog2_10);
+        v = ldexp(dt, -q);
     } else {
         v = exp10(fmin(fmax(t, 0.0), 7.0));
     }

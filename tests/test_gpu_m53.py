@@ -1,0 +1,136 @@
+"""GPU parity on the 53-species mechanism (N = 54): one wavefront per state,
+FP64 and FP32-factor (mixed) variants, plus the lane-per-state kernel on a
+small batch.  Same bar as the M13 tests: max relative error <= 1e-5 on T and
+on every Y_i whose oracle value exceeds 1e-8 (atol 1e-10, rtol 1e-6)."""
+import numpy as np
+import pytest
+
+from paper_1607_03884_amd import configs, gen
+from tests.parity import banner, integration_errors
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+K = 53
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch, torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def g53(torch_dev, m53_path):
+    from paper_1607_03884_amd import Mechanism
+    return Mechanism(m53_path)
+
+
+def _run(torch_dev, g, rows, dt, **opts):
+    torch, dev = torch_dev
+    for k, v in opts.items():
+        g.set_option(k, v)
+    y = torch.from_numpy(gen.to_soa(rows)).to(dev)
+    out = torch.full_like(y, float("nan"))
+    g.integrate(y, dt, configs.ATOL, configs.RTOL, y_out=out)
+    torch.cuda.synchronize()
+    st = g.stats(per_state=True)
+    return out.cpu().numpy().T, st
+
+
+def _reset(g):
+    for k, v in (("variant", "auto"), ("binning", 0), ("autotune", 0)):
+        g.set_option(k, v)
+
+
+@pytest.mark.parametrize("variant", ["wave", "mixed"])
+@pytest.mark.parametrize("dt", [1e-6, 1e-4])
+def test_cfg2_head_parity(torch_dev, g53, m53, dt, variant):
+    """First 1,024 PaSR-like M53 states, every state against the oracle."""
+    banner(f"M53 cfg2 head 1024 dt={dt} variant={variant}")
+    rows = configs.states_for(configs.WORKLOADS["cfg2"], 1024)
+    got, st = _run(torch_dev, g53, rows, dt, variant=variant)
+    _reset(g53)
+    ref, res = m53.integrate(rows, dt)
+    assert np.all(res["status"] == 0)
+    assert np.all(st["per_state_status"] == 0)
+    eT, eY = integration_errors(got, ref, K)
+    same = np.mean(st["per_state_steps"] == res["nstep"])
+    print(f"M53 dt={dt} {variant}: kernel {st['kernel_ms']:.1f} ms, steps/state {st['steps'] / len(rows):.1f}, "
+          f"max rel err T {eT:.2e} Y {eY:.2e}, identical step counts {same:.4f}, fp32 fallbacks {st['fp32_fallback']}")
+    assert eT <= TOL and eY <= TOL
+    assert same >= (0.98 if variant == "wave" else 0.3)
+    assert np.abs(got[:, 1:K + 1].sum(1) - rows[:, 1:K + 1].sum(1)).max() <= (1e-12 if variant == "wave" else 1e-9)
+    assert np.array_equal(got[:, -1], rows[:, -1])
+
+
+@pytest.mark.parametrize("variant", ["lane", "wave", "mixed"])
+@pytest.mark.parametrize("n", [1, 3, 65])
+def test_m53_ragged(torch_dev, g53, m53, n, variant):
+    banner(f"M53 ragged n={n} variant={variant}")
+    rows = configs.states_for(configs.WORKLOADS["cfg2"], 200)[-n:]
+    got, st = _run(torch_dev, g53, rows, 1e-6, variant=variant)
+    _reset(g53)
+    ref, res = m53.integrate(rows, 1e-6)
+    eT, eY = integration_errors(got, ref, K)
+    assert np.all(st["per_state_status"] == 0)
+    assert eT <= TOL and eY <= TOL
+    assert st["n_states"] == n
+
+
+def test_m53_failure_statuses(torch_dev, g53):
+    banner("M53 failure statuses")
+    rows = configs.states_for(configs.WORKLOADS["cfg2"], 5).copy()
+    rows[0, 4] = np.nan
+    rows[1, 0] = -10.0
+    rows[2, -1] = 0.0
+    for variant in ("wave", "mixed"):
+        got, st = _run(torch_dev, g53, rows, 1e-6, variant=variant)
+        assert list(st["per_state_status"]) == [3, 3, 3, 0, 0]
+        assert np.array_equal(got[:3], rows[:3], equal_nan=True)
+    got, st = _run(torch_dev, g53, rows[3:], 1e-6, variant="wave", nmax=2)
+    g53.set_option("nmax", 100000)
+    _reset(g53)
+    assert list(st["per_state_status"]) == [1, 1]
+
+
+@pytest.mark.parametrize("variant", ["wave", "mixed"])
+def test_cfg2_full_size_sampled(torch_dev, g53, m53, variant):
+    """All 131,072 cfg2 states at the large global step in the benchmark's
+    launch configuration (16 proxy bins): properties on every state, oracle
+    parity on a sample including the costliest states."""
+    dt = 1e-4
+    banner(f"M53 cfg2 131072 dt={dt} variant={variant}")
+    rows = configs.states_for(configs.WORKLOADS["cfg2"])
+    got, st = _run(torch_dev, g53, rows, dt, variant=variant, binning=16)
+    _reset(g53)
+    assert np.all(st["per_state_status"] == 0)
+    assert np.all(np.isfinite(got))
+    assert np.abs(got[:, 1:K + 1].sum(1) - rows[:, 1:K + 1].sum(1)).max() <= (1e-12 if variant == "wave" else 1e-9)
+    steps = st["per_state_steps"]
+    rng = np.random.default_rng(79)
+    top = np.argsort(steps)[-128:]
+    pick = np.unique(np.concatenate([top, rng.choice(len(rows), 384, replace=False)]))
+    ref, res = m53.integrate(rows[pick], dt)
+    eT, eY = integration_errors(got[pick], ref, K)
+    print(f"M53 cfg2 dt={dt} {variant}: kernel {st['kernel_ms']:.1f} ms, steps/state {st['steps'] / len(rows):.1f}, "
+          f"max rel err T {eT:.2e} Y {eY:.2e} on {len(pick)} sampled, fp32 fallbacks {st['fp32_fallback']}")
+    assert eT <= TOL and eY <= TOL
+
+
+def test_m53_schedule_invariance(torch_dev, g53):
+    """Bins and grid size never change a state's result (mixed variant,
+    including its FP64 re-run pass)."""
+    banner("M53 schedule invariance")
+    rows = configs.states_for(configs.WORKLOADS["cfg2"], 4096)
+    outs, steps = [], []
+    for opts in ({"binning": 0}, {"binning": 16}, {"binning": 0, "grid_pct": 50}):
+        got, st = _run(torch_dev, g53, rows, 1e-6, variant="mixed", **opts)
+        outs.append(got)
+        steps.append(st["per_state_steps"].copy())
+    g53.set_option("grid_pct", 100)
+    _reset(g53)
+    for o, s in zip(outs[1:], steps[1:]):
+        assert np.array_equal(o, outs[0])
+        assert np.array_equal(s, steps[0])
