@@ -6,6 +6,18 @@ workload integrated over one global time step with Radau IIA, once for each
 global step size of the workload (1e-6 s and 1e-4 s for the default
 262,144-state PaSR-like H2/CO-like workload).  Inputs are resident in HBM
 before timing starts.  Prints one JSON line.
+
+Forms (same library, same inputs):
+  plain          FP64 factors, one 16-lane group (N <= 16) or wavefront per
+                 state, persistent queue in input order, no predictor
+  binned         plain + autotuned cost bins of the work queue (proxy key)
+  learned        binned + the MLP first-step predictor; bins keyed by the
+                 predicted step counts
+  learned_mixed  learned with FP32 iteration-matrix factors (FP64 residuals)
+  mixed          binned with FP32 factors
+  lane           one state per lane (the paper's per-thread pattern)
+The headline form (--form) is timed over --steps steps; the others get one
+warm-up and one timed step each for the comparison block.
 """
 from __future__ import annotations
 
@@ -23,6 +35,15 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CUs x 64 FP64 FMA/clk x 2 flops x 2.4 GHz
 
 KERNEL_SOURCES = {"radau_group_kernel": ["rk_group.hip", "rk_internal.h"],
                   "radau_lane_kernel": ["rk_kernels.hip", "rk_internal.h"]}
+
+FORMS = {
+    "plain": dict(variant="wave", binning=0, autotune=0, predictor=False),
+    "binned": dict(variant="wave", binning=0, autotune=1, predictor=False),
+    "learned": dict(variant="wave", binning=0, autotune=1, predictor=True),
+    "learned_mixed": dict(variant="mixed", binning=0, autotune=1, predictor=True),
+    "mixed": dict(variant="mixed", binning=0, autotune=1, predictor=False),
+    "lane": dict(variant="lane", binning=0, autotune=0, predictor=False),
+}
 
 
 def measured_traffic(kernel: str, workload: str):
@@ -45,17 +66,24 @@ def measured_traffic(kernel: str, workload: str):
     return float(fields["traffic_bytes_per_dispatch"])
 
 
+def max_rel_err(got, ref, K):
+    import numpy as np
+    relT = np.abs(got[:, 0] - ref[:, 0]) / np.abs(ref[:, 0])
+    Yr = ref[:, 1:K + 1]
+    mask = Yr > 1e-8
+    relY = np.where(mask, np.abs(got[:, 1:K + 1] - Yr) / np.where(mask, Yr, 1.0), 0.0)
+    return float(max(relT.max(initial=0.0), relY.max(initial=0.0)))
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cfg1")
-    ap.add_argument("--variant", default="wave", help="lane | wave | mixed")
-    ap.add_argument("--binning", type=int, default=0, help="cost bins of the work queue (0 = input order)")
-    ap.add_argument("--autotune", type=int, default=1, help="1: let the library tune bins and grid per dt")
-    ap.add_argument("--compare", default="lane,mixed",
-                    help="other variants timed (1 warmup + 1 step each) for the comparison fields")
+    ap.add_argument("--form", default="learned", choices=sorted(FORMS))
+    ap.add_argument("--compare", default="plain,binned,learned_mixed,mixed,lane",
+                    help="other forms timed (1 warm-up + 1 step each) for the comparison block")
     ap.add_argument("--cpu-sample", type=int, default=16384)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
@@ -71,24 +99,66 @@ def main() -> int:
     import numpy as np
     import torch
 
-    from paper_1607_03884_amd import Mechanism, configs, gen
+    from paper_1607_03884_amd import Mechanism, configs, gen, predictor
     from paper_1607_03884_amd.flops import Costs
 
     wl = configs.WORKLOADS[args.workload]
     path = configs.mech_path(wl.mech)
     mech_def = gen.make_mechanism(configs.MECHS[wl.mech])
+    costs = Costs.of(mech_def)
     states = configs.states_for(wl)
     n = len(states)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     y = torch.from_numpy(gen.to_soa(states)).to(dev)
     out = torch.empty_like(y)
-    mech = Mechanism(path)
-    mech.set_option("variant", args.variant)
-    mech.set_option("binning", args.binning)
-    mech.set_option("autotune", args.autotune)
     stream = torch.cuda.current_stream()
-    print(f"[bench] {wl.name}: {n} states, mechanism {wl.mech} (K={mech.K}, R={mech.R}), dts {wl.dts}", flush=True)
+    have_pred = all(os.path.exists(predictor.path_for(wl.mech, dt)) for dt in wl.dts)
+
+    def make(form):
+        f = FORMS[form]
+        if f["predictor"] and not have_pred:
+            return None
+        m = Mechanism(path)
+        for k in ("variant", "binning", "autotune"):
+            m.set_option(k, f[k])
+        if f["predictor"]:
+            for dt in wl.dts:
+                m.set_option("predictor", predictor.path_for(wl.mech, dt))
+        return m
+
+    def launch(m, dt):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        m.integrate(y, dt, configs.ATOL, configs.RTOL, y_out=out, stream=stream)
+        b.record(stream)
+        return a, b
+
+    def launch_stats(m, dt, ms):
+        """counters of one (deterministic) launch, outside any timed region"""
+        m.integrate(y, dt, configs.ATOL, configs.RTOL, y_out=out, stream=stream)
+        st = m.stats()
+        fl = costs.flops(st)
+        tf = fl["flops"] / (ms * 1e-3) / 1e12
+        return st, fl, {"states_per_s": n / (ms * 1e-3), "kernel_ms": ms, "bins": st["nbins_used"],
+                        "grid": st["grid_used"], "steps_per_state": st["steps"] / n, "max_steps": st["max_steps"],
+                        "newton_per_step": st["newton_iters"] / max(st["steps"], 1),
+                        "newton_fail": st["newton_fail"], "rejected": st["rejected"],
+                        "jac_evals": st["jac_evals"], "lu_factor": st["lu_factor"], "failed": st["n_failed"],
+                        "fp32_fallback": st["fp32_fallback"], "predictor_kept": st["predictor_kept"],
+                        "predictor_fallback": st["predictor_fallback"], "D64_mean": st["d_mean64"],
+                        "D32_mean": st["d_mean32"], "gflop": fl["flops"] / 1e9,
+                        "gtrans": fl["transcendentals"] / 1e9, "tflops": tf,
+                        "fp64_frac": tf / FP64_VECTOR_PEAK_TFLOPS}
+
+    form = args.form
+    if FORMS[form]["predictor"] and not have_pred:
+        print(f"[bench] no predictor files for {wl.mech}; headline form falls back to 'binned'", flush=True)
+        form = "binned"
+    mech = make(form)
+    print(f"[bench] {wl.name}: {n} states, mechanism {wl.mech} (K={mech.K}, R={mech.R}), dts {wl.dts}, "
+          f"form {form}", flush=True)
 
     for _ in range(args.warmup):
         for dt in wl.dts:
@@ -101,12 +171,7 @@ def main() -> int:
     t0 = time.perf_counter()
     for _ in range(args.steps):
         for dt in wl.dts:
-            a = torch.cuda.Event(enable_timing=True)
-            b = torch.cuda.Event(enable_timing=True)
-            a.record(stream)
-            mech.integrate(y, dt, configs.ATOL, configs.RTOL, y_out=out, stream=stream)
-            b.record(stream)
-            events[dt].append((a, b))
+            events[dt].append(launch(mech, dt))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     sec_per_step = (t1 - t0) / args.steps
@@ -122,86 +187,77 @@ def main() -> int:
         print("[bench] calibration copy: 536870912 bytes read, 536870912 bytes written", flush=True)
         del src, dst
 
-    # counters of one (identical, deterministic) launch per dt, outside the timed region
-    costs = Costs.of(mech_def)
-    per_dt = {}
-    gpu_out = {}
+    per_dt, gpu_out = {}, {}
     tot_flops = tot_ms = 0.0
     for dt in wl.dts:
-        mech.integrate(y, dt, configs.ATOL, configs.RTOL, y_out=out, stream=stream)
-        st = mech.stats()
-        fl = costs.flops(st)
+        st, fl, rec = launch_stats(mech, dt, kernel_ms[dt])
         gpu_out[dt] = out.cpu().numpy().T.copy()
         tot_flops += fl["flops"]
         tot_ms += kernel_ms[dt]
-        per_dt[f"{dt:g}"] = {"states_per_s": n / (kernel_ms[dt] * 1e-3), "kernel_ms": kernel_ms[dt],
-                             "bins": st["nbins_used"], "grid": st["grid_used"], "fp32_fallback": st["fp32_fallback"],
-                             "steps_per_state": st["steps"] / n, "max_steps": st["max_steps"],
-                             "newton_per_step": st["newton_iters"] / max(st["steps"], 1),
-                             "jac_evals": st["jac_evals"], "lu_factor": st["lu_factor"],
-                             "failed": st["n_failed"], "D64_mean": st["d_mean64"], "D32_mean": st["d_mean32"],
-                             "gflop": fl["flops"] / 1e9, "gtrans": fl["transcendentals"] / 1e9}
+        per_dt[f"{dt:g}"] = rec
     achieved = tot_flops / (tot_ms * 1e-3) / 1e12
-    kname = {"lane": "radau_lane_kernel", "wave": "radau_group_kernel"}.get(args.variant, args.variant)
+    kname = "radau_lane_kernel" if FORMS[form]["variant"] == "lane" else "radau_group_kernel"
     roofline = {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": measured_traffic(kname, wl.name),
-                "kernel": kname, "flops_per_launch": tot_flops / len(wl.dts)}
+                "kernel": kname, "flops_per_launch": tot_flops / len(wl.dts),
+                "note": "launch time includes the predictor network and bin sort (separate small kernels)"}
 
-    # the other variants, same inputs, for the comparison fields (not the headline value)
     compare = {}
-    for var in [v for v in args.compare.split(",") if v and v != args.variant]:
-        other = Mechanism(path)
-        other.set_option("variant", var)
-        other.set_option("autotune", args.autotune if var != "lane" else 0)
-        rate = {}
+    for other in [v for v in args.compare.split(",") if v and v != form]:
+        m = make(other)
+        if m is None:
+            continue
+        recs, tot = {}, 0.0
         for dt in wl.dts:
-            other.integrate(y, dt, configs.ATOL, configs.RTOL, y_out=out, stream=stream)
-            a = torch.cuda.Event(enable_timing=True)
-            b = torch.cuda.Event(enable_timing=True)
-            a.record(stream)
-            other.integrate(y, dt, configs.ATOL, configs.RTOL, y_out=out, stream=stream)
-            b.record(stream)
+            m.integrate(y, dt, configs.ATOL, configs.RTOL, y_out=out, stream=stream)
+            a, b = launch(m, dt)
             torch.cuda.synchronize()
-            rate[f"{dt:g}"] = n / (a.elapsed_time(b) * 1e-3)
-        compare[var] = {"states_per_s": rate,
-                        "per_step_states_per_s": n * len(wl.dts) / sum(n / r for r in rate.values())}
-        other.close()
-        print(f"[bench] compared {var}: {compare[var]['per_step_states_per_s']:.0f} states/s", flush=True)
+            ms = a.elapsed_time(b)
+            tot += ms
+            _, _, recs[f"{dt:g}"] = launch_stats(m, dt, ms)
+        m.close()
+        compare[other] = {"per_step_states_per_s": n * len(wl.dts) / (tot * 1e-3), "per_dt": recs}
+        print(f"[bench] compared {other}: {compare[other]['per_step_states_per_s']:.0f} states/s", flush=True)
 
-    cpu = None
-    parity = None
+    cpu = parity = None
     if not args.no_cpu_baseline:
         import oracle
+        from oracle import predict as opred
         m_or = oracle.Mech(path)
         sample = states[:min(args.cpu_sample, n)]
         threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
         c0 = time.perf_counter()
-        worst = 0.0
-        for dt in wl.dts:
-            ref, res = m_or.integrate(sample, dt, configs.ATOL, configs.RTOL, nthreads=threads)
-            g = gpu_out[dt][:len(sample)]
-            relT = np.abs(g[:, 0] - ref[:, 0]) / ref[:, 0]
-            Yr = ref[:, 1:mech.K + 1]
-            mask = Yr > 1e-8
-            relY = np.where(mask, np.abs(g[:, 1:mech.K + 1] - Yr) / np.where(mask, Yr, 1.0), 0.0)
-            worst = max(worst, float(relT.max()), float(relY.max()))
+        cold = {dt: m_or.integrate(sample, dt, configs.ATOL, configs.RTOL, nthreads=threads)[0] for dt in wl.dts}
         c1 = time.perf_counter()
         cpu = {"value": len(sample) * len(wl.dts) / (c1 - c0), "unit": "states/s", "cores": threads,
                "kind": "oracle",
                "sample": f"first {len(sample)} states of the {n}-state set (same PaSR-like mix), each dt"}
-        parity = {"max_rel_err_vs_oracle": worst, "sample": len(sample), "tol": 1e-5}
+        parity = {"sample": len(sample), "tol": 1e-5,
+                  "vs_oracle_cold": max(max_rel_err(gpu_out[dt][:len(sample)], cold[dt], mech.K) for dt in wl.dts)}
+        if FORMS[form]["predictor"]:
+            worst = 0.0
+            for dt in wl.dts:
+                pr = opred.load(predictor.path_for(wl.mech, dt))
+                h, z, _ = opred.warm_start(pr, sample, configs.ATOL, configs.RTOL, dt)
+                ref, _ = m_or.integrate_warm(sample, dt, h, z, configs.ATOL, configs.RTOL, nthreads=threads)
+                worst = max(worst, max_rel_err(gpu_out[dt][:len(sample)], ref, mech.K))
+            parity["vs_oracle_same_start"] = worst
+            parity["note"] = ("the learned form is judged against the oracle started from the same "
+                              "prediction; vs_oracle_cold is the deviation from a cold-started oracle")
 
     value = n * len(wl.dts) / sec_per_step
+    fdesc = FORMS[form]
     line = {
-        "metric": "states integrated/s per global step (dt=1e-6,1e-4 s)",
+        "metric": "states integrated/s per global step (dt=1e-6,1e-4 s), learned+FP32-LU vs plain FP64",
         "value": value, "unit": "states/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": sec_per_step * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"{wl.name}: synthetic {wl.mech} ({mech.K} species, {mech.R} reversible reactions), "
                                f"{n} PaSR-like states, one global step at each of {list(wl.dts)} s",
                    "n_states": n, "dts": list(wl.dts), "atol": configs.ATOL, "rtol": configs.RTOL,
-                   "variant": args.variant, "autotune": args.autotune, "binning": args.binning,
-                   "path": "mixed FP32 factors" if args.variant == "mixed" else "plain FP64"},
+                   "form": form, "variant": fdesc["variant"], "autotune": fdesc["autotune"],
+                   "predictor": fdesc["predictor"],
+                   "factors": "FP32 (FP64 residuals)" if fdesc["variant"] == "mixed" else "FP64"},
         "per_dt": per_dt,
         "compare": compare,
         "roofline": roofline,
