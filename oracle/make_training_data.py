@@ -36,9 +36,16 @@ def make(mech: str, n: int, dts=(configs.DT_SMALL, configs.DT_LARGE), nthreads: 
     K = configs.MECHS[mech].n_species
     m = oracle.Mech(configs.mech_path(mech))
     states = gen.pasr_like_states(K, n, TRAIN_SEED, configs.load_templates(mech))
+    chunk = 8192
     for dt in dts:
         t0 = time.time()
-        out, res, z = m.integrate_first_step(states, dt, configs.ATOL, configs.RTOL, nthreads=nthreads)
+        parts = []
+        for i in range(0, n, chunk):
+            parts.append(m.integrate_first_step(states[i:i + chunk], dt, configs.ATOL, configs.RTOL,
+                                                nthreads=nthreads))
+            print(f"{mech} dt={dt:g}: {min(n, i + chunk)}/{n} states ({time.time() - t0:.1f} s)", flush=True)
+        res = np.concatenate([p[1] for p in parts])
+        z = np.concatenate([p[2] for p in parts])
         np.savez(path_for(mech, dt), states=states, z_first=z, h_first=res["h_first"], nstep=res["nstep"],
                  status=res["status"], dt=dt, atol=configs.ATOL, rtol=configs.RTOL)
         print(f"{mech} dt={dt:g}: {n} states in {time.time() - t0:.1f} s -> {path_for(mech, dt)}", flush=True)

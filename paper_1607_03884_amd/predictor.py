@@ -84,6 +84,7 @@ def train(mech: str, dt: float, data: Dict[str, np.ndarray], hidden=(128, 128), 
     ones = torch.ones(batch, dtype=torch.float32, device=dev)
     loss = torch.empty(1, dtype=torch.float32, device=dev)
     ntr = len(tr)
+    epochs = max(epochs, math.ceil(1700 * batch / ntr))    # at least ~1,700 updates on small sets
     steps = epochs * (ntr // batch)
     t0 = time.time()
     k = 0

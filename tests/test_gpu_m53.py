@@ -134,3 +134,56 @@ def test_m53_schedule_invariance(torch_dev, g53):
     for o, s in zip(outs[1:], steps[1:]):
         assert np.array_equal(o, outs[0])
         assert np.array_equal(s, steps[0])
+
+
+def _oracle_warm(m53, rows, dt):
+    from oracle import predict as opred
+    from paper_1607_03884_amd import predictor
+    pr = opred.load(predictor.path_for("M53", dt))
+    h, z, _ = opred.warm_start(pr, rows, configs.ATOL, configs.RTOL, dt)
+    return m53.integrate_warm(rows, dt, h, z)
+
+
+@pytest.mark.parametrize("variant", ["wave", "mixed"])
+@pytest.mark.parametrize("dt", [1e-6, 1e-4])
+def test_cfg3_learned_parity(torch_dev, g53, m53, dt, variant):
+    """The M53 predictor (55 -> 128 -> 128 -> 164, GELU, BF16 weights) on the
+    first 1,024 cfg2 states: every state against the oracle started from the
+    same prediction."""
+    from paper_1607_03884_amd import predictor
+    banner(f"M53 learned 1024 dt={dt} variant={variant}")
+    rows = configs.states_for(configs.WORKLOADS["cfg2"], 1024)
+    g53.set_option("predictor", predictor.path_for("M53", dt))
+    got, st = _run(torch_dev, g53, rows, dt, variant=variant)
+    g53.set_option("predictor", "none")
+    _reset(g53)
+    ref, res = _oracle_warm(m53, rows, dt)
+    assert np.all(res["status"] == 0) and np.all(st["per_state_status"] == 0)
+    eT, eY = integration_errors(got, ref, K)
+    same = np.mean(st["per_state_steps"] == res["nstep"])
+    print(f"M53 learned dt={dt} {variant}: kernel {st['kernel_ms']:.1f} ms, steps/state {st['steps'] / len(rows):.1f}, "
+          f"kept {st['predictor_kept']} fallback {st['predictor_fallback']}, max rel err T {eT:.2e} Y {eY:.2e}, "
+          f"identical step counts {same:.4f}")
+    assert eT <= TOL and eY <= TOL
+    assert st["predictor_kept"] + st["predictor_fallback"] == len(rows)
+
+
+@pytest.mark.parametrize("dt", [1e-6, 1e-4])
+def test_cfg3_learned_ablation(torch_dev, g53, dt):
+    """Full 131,072-state cfg2 set: cold start with proxy bins against the
+    learned first step with bins from predicted step counts."""
+    from paper_1607_03884_amd import predictor
+    banner(f"M53 learned ablation dt={dt}")
+    rows = configs.states_for(configs.WORKLOADS["cfg2"])
+    _, cold = _run(torch_dev, g53, rows, dt, variant="wave", binning=16)
+    g53.set_option("predictor", predictor.path_for("M53", dt))
+    _, learned = _run(torch_dev, g53, rows, dt, variant="wave", binning=16)
+    g53.set_option("predictor", "none")
+    _reset(g53)
+    n = len(rows)
+    for tag, st in (("cold+proxy bins", cold), ("learned+predicted bins", learned)):
+        print(f"{tag:>24}: kernel {st['kernel_ms']:8.1f} ms steps/state {st['steps'] / n:7.2f} "
+              f"rejected {st['rejected']:8d} newton fails {st['newton_fail']:8d} kept {st['predictor_kept']}")
+    assert np.all(learned["per_state_status"] == 0)
+    assert learned["newton_fail"] < cold["newton_fail"]
+    assert learned["steps"] < cold["steps"]
