@@ -15,17 +15,37 @@ HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
                "-Wall", "-Wno-unused-function"]
 
 
-def build_library(verbose: bool = False) -> str:
+def build_library(verbose: bool = False, csrc: str = CSRC, out: str = OUT) -> str:
+    """Compile every source to an object (in parallel), then link the shared
+    library.  Objects go to _build/ next to the output."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = OUT + f".tmp{os.getpid()}"
-    cmd = [hipcc] + HIPCC_FLAGS + [os.path.join(CSRC, s) for s in SOURCES] + ["-o", tmp]
-    r = subprocess.run(cmd, capture_output=True, text=True)
+    objdir = os.path.join(os.path.dirname(out), "_build")
+    os.makedirs(objdir, exist_ok=True)
+    compile_flags = [f for f in HIPCC_FLAGS if f != "-shared"]
+    procs = []
+    for s in SOURCES:
+        obj = os.path.join(objdir, s + f".{os.getpid()}.o")
+        cmd = [hipcc] + compile_flags + ["-c", os.path.join(csrc, s), "-o", obj]
+        procs.append((s, obj, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)))
+    objs, errors = [], []
+    for s, obj, p in procs:
+        so, se = p.communicate()
+        if p.returncode != 0:
+            errors.append(f"{s}:\n{so}{se}")
+        elif verbose and se:
+            print(se)
+        objs.append(obj)
+    if errors:
+        raise RuntimeError("hipcc failed:\n" + "\n".join(errors))
+    tmp = out + f".tmp{os.getpid()}"
+    r = subprocess.run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", tmp],
+                       capture_output=True, text=True)
+    for o in objs:
+        os.remove(o)
     if r.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + r.stdout + r.stderr)
-    if verbose:
-        print(r.stderr)
-    os.replace(tmp, OUT)
-    return OUT
+        raise RuntimeError("link failed:\n" + r.stdout + r.stderr)
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -648,8 +648,11 @@ __global__ void collect_fallback_kernel(const int32_t *__restrict__ cnt, int64_t
 // takes the next state from the queue in the next iteration without waiting
 // for the other groups of its wavefront.  The wavefront leaves the loop when
 // no group holds a state.
+// G = 16: at most 256 registers, so two wavefronts share each SIMD (the LDS
+// slices of eight 4-state blocks fit a CU); the few spills cost far less than
+// the latency the second wavefront hides.
 template <typename S, int G, int NC>
-__global__ __launch_bounds__(64) void radau_group_kernel(DevMech m, RadauParams rp, int64_t n,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(G == 16 ? 2 : 1))) void radau_group_kernel(DevMech m, RadauParams rp, int64_t n,
                                                          const double *__restrict__ yin, double *__restrict__ yout,
                                                          int32_t *__restrict__ cnt, int *__restrict__ queue,
                                                          const int *__restrict__ order,
