@@ -33,7 +33,7 @@ if ROOT not in sys.path:
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CUs x 64 FP64 FMA/clk x 2 flops x 2.4 GHz
 
-KERNEL_SOURCES = {"radau_group_kernel": ["rk_group.hip", "rk_internal.h"],
+KERNEL_SOURCES = {"radau_group_kernel": ["rk_group_impl.h", "rk_group16.hip", "rk_internal.h"],
                   "radau_lane_kernel": ["rk_kernels.hip", "rk_internal.h"]}
 
 FORMS = {

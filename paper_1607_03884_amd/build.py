@@ -6,7 +6,8 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["rk_api.cpp", "rk_kernels.hip", "rk_group.hip", "rk_mlp.hip", "rk_pred.hip"]
+SOURCES = ["rk_api.cpp", "rk_kernels.hip", "rk_group.hip", "rk_group16.hip", "rk_group64.hip", "rk_mlp.hip",
+           "rk_pred.hip"]
 OUT = os.path.join(HERE, "librkchem.so")
 
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

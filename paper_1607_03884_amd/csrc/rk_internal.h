@@ -83,6 +83,15 @@ hipError_t launch_radau_group(const DevMech &m, const RadauParams &p, int64_t n,
                               int32_t *counters, int *queue, int *fb_list, const int *order, const double *pred,
                               bool mixed, int grid, hipStream_t st);
 int group_max_blocks(int N, int R);
+// per-family entry points (rk_group16.hip, rk_group64.hip): NC = register columns
+hipError_t launch_group16(int NC, bool fp32, const DevMech &m, const RadauParams &p, int64_t n, const double *yin,
+                          double *yout, int32_t *cnt, int *queue, const int *order, const int *work_n,
+                          const double *pred, int grid, hipStream_t st);
+hipError_t launch_group64(int NC, bool fp32, const DevMech &m, const RadauParams &p, int64_t n, const double *yin,
+                          double *yout, int32_t *cnt, int *queue, const int *order, const int *work_n,
+                          const double *pred, int grid, hipStream_t st);
+int occupancy_group16(int NC, size_t lds);
+int occupancy_group64(int NC, size_t lds);
 hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t st);
 size_t group_lds_bytes(int N, int R);
 
