@@ -112,12 +112,19 @@ __device__ __forceinline__ int gpivot(double mag, bool used, int lane) {
 // dimension NC + 1, so lanes reading down a column hit distinct banks.
 struct GL {
     double *C, *h, *s, *rec, *J, *prow, *vx;
+    double *zs;       // previous step's stage values, [3][NC] (parked here, not in registers)
+    double *hist;     // h of the last accepted step, its error, h of the last step, pressure, time
+    double *f0s;      // f(y0) of the current step, [NC]
+    int *ctr;         // rarely read per-state counters (lane 0 updates them)
 };
+
+// per-state counters kept in LDS
+enum { K_NREJ = 0, K_NNEWT, K_NNF, K_NFEV, K_NJEV, K_NLU, K_NCTR };
 
 __host__ __device__ constexpr int rec_chunk(int R) { return R < 64 ? R : 64; }
 
 __host__ __device__ constexpr int group_lds_doubles(int NC, int R) {
-    return 3 * NC + 8 * rec_chunk(R) + NC * (NC + 1) + 2 * NC + NC;
+    return 3 * NC + 8 * rec_chunk(R) + NC * (NC + 1) + 2 * NC + NC + 3 * NC + 5 + NC + (K_NCTR + 1) / 2;
 }
 
 template <int NC>
@@ -130,6 +137,10 @@ __device__ __forceinline__ GL group_lds(double *base, int R) {
     L.J = L.rec + 8 * rec_chunk(R);
     L.prow = L.J + NC * (NC + 1);
     L.vx = L.prow + 2 * NC;
+    L.zs = L.vx + NC;
+    L.hist = L.zs + 3 * NC;
+    L.f0s = L.hist + 5;
+    L.ctr = reinterpret_cast<int *>(L.f0s + NC);
     return L;
 }
 
@@ -669,12 +680,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(G == 16 ? 2 
     const int PD = 3 * N + 2;
     bool have = false, drained = false;
     int64_t s = 0;
-    double P = 0.0, y = 0.0, f0 = 0.0, sc = 1.0, t = 0.0, h = 0.0;
-    double eta = 1.0, theta = 1.0, hacc = 0.0, erracc = 1e-2, hlast = 0.0;
-    double Zs1 = 0.0, Zs2 = 0.0, Zs3 = 0.0;
+    // per-state values that are read rarely live in LDS: pressure L.hist[3],
+    // time L.hist[4], f(y0) L.f0s; the error weights are recomputed from y
+    double y = 0.0, h = 0.0;
+    auto scw = [&]() { return comp ? atol + rtol * fabs(y) : 1.0; };
+    double eta = 1.0, theta = 1.0;
     bool last = false, first = true, reject = false, jac_fresh = false;
     int action = ACT_JAC;
-    int status = 0, nstep = 0, nacc = 0, nrej = 0, nnewt = 0, nnf = 0, nfev = 0, njev = 0, nlu = 0;
+    int status = 0, nstep = 0, nacc = 0;
+    // counter increments go to LDS (lane 0 of the group), read once at the end
+    auto bump = [&](int k, int v) {
+        if (r == 0) L.ctr[k] += v;
+    };
 
     for (;;) {
         // ---- refill: take the next state of the queue --------------------------
@@ -686,11 +703,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(G == 16 ? 2 
                 drained = true;
             } else {
                 s = order ? (int64_t)order[qi] : (int64_t)qi;
-                P = yin[(size_t)(K + 1) * n + s];
+                const double P = yin[(size_t)(K + 1) * n + s];
+                L.hist[3] = P;
                 y = comp ? yin[(size_t)r * n + s] : 0.0;
                 const bool bad_l = (comp && !isfinite(y)) || (r == 0 && !(y > 0.0)) ||
                                    (r == 0 && !(P > 0.0 && isfinite(P)));
-                nstep = nacc = nrej = nnewt = nnf = nfev = njev = nlu = 0;
+                nstep = nacc = 0;
+                if (r < K_NCTR) L.ctr[r] = 0;
                 if (gsum<G>(bad_l ? 1.0 : 0.0) > 0.0) {
                     status = RK_ST_NONFINITE;
                     if (comp) yout[(size_t)r * n + s] = y;
@@ -703,7 +722,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(G == 16 ? 2 
                     have = true;
                     status = RK_ST_OK;
                     flags = 0;
-                    t = 0.0;
+                    L.hist[4] = 0.0;
                     warm = pred != nullptr;
                     h = rp.h0;
                     if (warm) {
@@ -713,19 +732,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(G == 16 ? 2 
                         warm = rp.pred_use != 0;
                     }
                     last = false;
-                    if (t + 1.0001 * h >= dt) { h = dt - t; last = true; }
-                    f0 = rhs_g<G>(m, L, r, y, P);
-                    nfev = 1;
-                    sc = comp ? atol + rtol * fabs(y) : 1.0;
+                    if (1.0001 * h >= dt) { h = dt; last = true; }
+                    const double f0 = rhs_g<G>(m, L, r, y, P);
+                    if (r < NC) L.f0s[r] = f0;
+                    bump(K_NFEV, 1);
                     first = true;
                     reject = false;
                     jac_fresh = false;
                     eta = 1.0;
                     theta = 1.0;
-                    hacc = h;
-                    erracc = 1e-2;
-                    hlast = h;
-                    Zs1 = Zs2 = Zs3 = 0.0;
+                    L.hist[0] = h;        // h of the last accepted step
+                    L.hist[1] = 1e-2;     // its error
+                    L.hist[2] = h;        // h of the last step (stage extrapolation)
                     ndiv_row = 0;
                     action = ACT_JAC;
                 }
@@ -736,8 +754,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(G == 16 ? 2 
 
         // ---- one step attempt ---------------------------------------------------
         if (action == ACT_JAC) {
-            jac_g<G, NC>(m, L, r, y, P);
-            ++njev;
+            jac_g<G, NC>(m, L, r, y, L.hist[3]);
+            bump(K_NJEV, 1);
             jac_fresh = true;
             action = ACT_LU;
         }
@@ -748,7 +766,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(G == 16 ? 2 
                 // equilibrate: E'' = diag(1/(sc_r m_r)) E diag(sc_c).  The column
                 // scaling is applied in FP64 before rounding, the row factor m_r (the
                 // power of two at or below the row maximum, so exact) afterwards
-                const double scv = comp ? sc : 1.0;
+                const double scv = scw();
                 double m1 = 0.0, m2 = 0.0;
                 const double isc = 1.0 / scv;
 #pragma unroll
@@ -773,7 +791,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(G == 16 ? 2 
                 }
                 E1.rs = isc * i1;
                 E2.rs = isc * i2;
-                E1.cs = E2.cs = comp ? sc : 1.0;
+                E1.cs = E2.cs = scv;
                 sync_wave();
             } else {
 #pragma unroll
@@ -790,14 +808,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(G == 16 ? 2 
             }
             factor_real<S, G>(E1, L, r, N);
             factor_cplx<S, G>(E2, L, r, N);
-            ++nlu;
+            bump(K_NLU, 1);
         }
         action = ACT_SAME;
         bool done = false;
         if (nstep >= rp.nmax) {
             status = RK_ST_STEP_LIMIT;
             done = true;
-        } else if (0.1 * h <= kU * t || h < 1e-300) {   // the step no longer advances t
+        } else if (0.1 * h <= kU * L.hist[4] || h < 1e-300) {   // the step no longer advances t
             status = RK_ST_H_UNDERFLOW;
             done = true;
         } else {
@@ -812,7 +830,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(G == 16 ? 2 
                 Z2 = zw ? ps[N + r] : 0.0;
                 Z3 = zw ? ps[2 * N + r] : 0.0;
             } else {
-                const double c1 = rp.c1, c2 = rp.c2, q = h / hlast;
+                const double c1 = rp.c1, c2 = rp.c2, q = h / L.hist[2];
+                const double Zs1 = r < NC ? L.zs[r] : 0.0;
+                const double Zs2 = r < NC ? L.zs[NC + r] : 0.0;
+                const double Zs3 = r < NC ? L.zs[2 * NC + r] : 0.0;
                 const double t1 = 1.0 + c1 * q, t2 = 1.0 + c2 * q, t3 = 1.0 + q;
                 const double d01 = Zs1 / c1, d12 = (Zs2 - Zs1) / (c2 - c1), d23 = (Zs3 - Zs2) / (1.0 - c2);
                 const double d012 = (d12 - d01) / c2, d123 = (d23 - d12) / (1.0 - c1);
@@ -836,12 +857,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(G == 16 ? 2 
 #pragma nounroll
                 for (int i = 0; i < 3; ++i) {
                     const double zi = i == 0 ? Z1 : (i == 1 ? Z2 : Z3);
-                    const double fi = rhs_g<G>(m, L, r, y + zi, P);
+                    const double fi = rhs_g<G>(m, L, r, y + zi, L.hist[3]);
                     F1 = i == 0 ? fi : F1;
                     F2 = i == 1 ? fi : F2;
                     F3 = i == 2 ? fi : F3;
                 }
-                nfev += 3;
+                bump(K_NFEV, 3);
                 const double gh = rp.g / h, ah = rp.a / h, bh = rp.b / h;
                 const double G1 = rp.Ti[0] * F1 + rp.Ti[1] * F2 + rp.Ti[2] * F3;
                 const double G2 = rp.Ti[3] * F1 + rp.Ti[4] * F2 + rp.Ti[5] * F3;
@@ -864,8 +885,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(G == 16 ? 2 
                 const double dZ1 = rp.T[0] * dW1 + rp.T[1] * dW2 + rp.T[2] * dW3;
                 const double dZ2 = rp.T[3] * dW1 + rp.T[4] * dW2 + rp.T[5] * dW3;
                 const double dZ3 = rp.T[6] * dW1 + rp.T[7] * dW2 + rp.T[8] * dW3;
-                ++nnewt;
+                bump(K_NNEWT, 1);
                 newt = it;
+                const double sc = scw();
                 const double dn = sqrt(gsum<G>(comp ? (dZ1 * dZ1 + dZ2 * dZ2 + dZ3 * dZ3) / (sc * sc) : 0.0) / (3 * N));
                 if (!isfinite(dn)) { diverged = true; break; }
                 if (it >= 2) {
@@ -883,20 +905,20 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(G == 16 ? 2 
             if (!converged && warm) {
                 // the prediction did not converge: restart the state exactly as a cold
                 // start (default first step, zero starting values, controller memory)
-                ++nnf;
+                bump(K_NNF, 1);
                 warm = false;
                 flags |= kFlagPredFallback;
                 h = rp.h0;
                 last = false;
-                if (t + 1.0001 * h >= dt) { h = dt - t; last = true; }
+                if (1.0001 * h >= dt) { h = dt; last = true; }
                 eta = 1.0;
                 theta = 1.0;
-                hacc = h;
-                erracc = 1e-2;
-                hlast = h;
+                L.hist[0] = h;
+                L.hist[1] = 1e-2;
+                L.hist[2] = h;
                 action = ACT_LU;
             } else if (!converged) {
-                ++nnf;
+                bump(K_NNF, 1);
                 h *= 0.5;
                 reject = true;
                 last = false;
@@ -913,13 +935,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(G == 16 ? 2 
                 const double dz = (rp.d[0] * Z1 + rp.d[1] * Z2 + rp.d[2] * Z3) * invh;
                 const double sc2 = comp ? atol + rtol * fmax(fabs(y), fabs(y + Z3)) : 1.0;
                 const double gh = rp.g / h;
-                double v = comp ? f0 + dz : 0.0;
+                double v = comp ? L.f0s[r] + dz : 0.0;
                 double ev = solve_real<S, G>(E1, r, N, v);
                 if constexpr (kMixed) ev += solve_real<S, G>(E1, r, N, v - ematvec<NC>(L, r, N, gh, ev));   // FP64 residual
                 double err = fmax(sqrt(gsum<G>(comp ? (ev / sc2) * (ev / sc2) : 0.0) / N), 1e-10);
                 if (err >= 1.0 && (first || reject)) {
-                    const double fe = rhs_g<G>(m, L, r, y + ev, P);
-                    ++nfev;
+                    const double fe = rhs_g<G>(m, L, r, y + ev, L.hist[3]);
+                    bump(K_NFEV, 1);
                     v = comp ? fe + dz : 0.0;
                     ev = solve_real<S, G>(E1, r, N, v);
                     if constexpr (kMixed) ev += solve_real<S, G>(E1, r, N, v - ematvec<NC>(L, r, N, gh, ev));
@@ -935,24 +957,29 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(G == 16 ? 2 
                     ndiv_row = 0;
                     ++nacc;
                     if (nacc > 1) {
-                        double fg = (hacc / h) * pow(err * err / erracc, 0.25) / 0.9;
+                        double fg = (L.hist[0] / h) * pow(err * err / L.hist[1], 0.25) / 0.9;
                         fg = fmax(0.125, fmin(5.0, fg));
                         quot = fmax(quot, fg);
                         hnew = h / quot;
                     }
-                    hacc = h;
-                    erracc = fmax(1e-2, err);
-                    Zs1 = Z1; Zs2 = Z2; Zs3 = Z3;
-                    hlast = h;
+                    L.hist[0] = h;
+                    L.hist[1] = fmax(1e-2, err);
+                    L.hist[2] = h;
+                    if (r < NC) {
+                        L.zs[r] = Z1;
+                        L.zs[NC + r] = Z2;
+                        L.zs[2 * NC + r] = Z3;
+                    }
                     y = comp ? y + Z3 : 0.0;
-                    sc = comp ? atol + rtol * fabs(y) : 1.0;
-                    t = last ? dt : t + h;
+                    const double t = last ? dt : L.hist[4] + h;
+                    L.hist[4] = t;
                     jac_fresh = false;
                     if (last) {
                         done = true;
                     } else {
-                        f0 = rhs_g<G>(m, L, r, y, P);
-                        ++nfev;
+                        const double f0 = rhs_g<G>(m, L, r, y, L.hist[3]);
+                        if (r < NC) L.f0s[r] = f0;
+                        bump(K_NFEV, 1);
                         if (reject) hnew = fmin(hnew, h);
                         reject = false;
                         if (t + 1.0001 * hnew >= dt) {   // last step: no tail shorter than 1e-4 h
@@ -970,7 +997,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(G == 16 ? 2 
                         }
                     }
                 } else {
-                    ++nrej;
+                    bump(K_NREJ, 1);
                     reject = true;
                     last = false;
                     h = first ? 0.1 * h : hnew;
@@ -981,16 +1008,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(G == 16 ? 2 
         if (done) {
             if (comp) yout[(size_t)r * n + s] = y;
             if (r == 0) {
-                yout[(size_t)(K + 1) * n + s] = P;
+                yout[(size_t)(K + 1) * n + s] = L.hist[3];
                 cnt[(size_t)C_STATUS * n + s] = status;
                 cnt[(size_t)C_NSTEP * n + s] = nstep;
                 cnt[(size_t)C_NACC * n + s] = nacc;
-                cnt[(size_t)C_NREJ * n + s] = nrej;
-                cnt[(size_t)C_NNEWT * n + s] = nnewt;
-                cnt[(size_t)C_NNFAIL * n + s] = nnf;
-                cnt[(size_t)C_NFEV * n + s] = nfev;
-                cnt[(size_t)C_NJEV * n + s] = njev;
-                cnt[(size_t)C_NLU * n + s] = nlu;
+                cnt[(size_t)C_NREJ * n + s] = L.ctr[K_NREJ];
+                cnt[(size_t)C_NNEWT * n + s] = L.ctr[K_NNEWT];
+                cnt[(size_t)C_NNFAIL * n + s] = L.ctr[K_NNF];
+                cnt[(size_t)C_NFEV * n + s] = L.ctr[K_NFEV];
+                cnt[(size_t)C_NJEV * n + s] = L.ctr[K_NJEV];
+                cnt[(size_t)C_NLU * n + s] = L.ctr[K_NLU];
                 // the FP64 pass over handed-back states keeps the mixed pass's flags
                 const int32_t prev = work_n ? cnt[(size_t)C_FLAGS * n + s] : 0;
                 cnt[(size_t)C_FLAGS * n + s] = prev | flags | (status == kStatusFallback ? kFlagFp32Fallback : 0);
