@@ -347,16 +347,22 @@ bool is_device_ptr(const void *ptr) {
     return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
 }
 
-int ensure_workspace(rk_mech *m, int64_t n) {
-    const size_t need = rk::lane_scratch_doubles(m->K, n);
+// per-lane working set of the lane-per-state kernel and the debug kernels
+// (only they use it: the group kernels keep everything on chip)
+int ensure_lane_scratch(rk_mech *m, int64_t n) {
+    const size_t need = rk::lane_scratch_doubles(m->K, std::max<int64_t>(n, 1));
     if (need > m->scratch_cap) {
         if (m->scratch) { (void)hipDeviceSynchronize(); (void)hipFree(m->scratch); m->scratch = nullptr; m->scratch_cap = 0; }
         if (hipMalloc(&m->scratch, need * sizeof(double)) != hipSuccess) {
             (void)hipGetLastError();
-            return fail(RK_ENOMEM, "cannot allocate integrator workspace");
+            return fail(RK_ENOMEM, "cannot allocate the lane-kernel workspace");
         }
         m->scratch_cap = need;
     }
+    return RK_OK;
+}
+
+int ensure_workspace(rk_mech *m, int64_t n) {
     if (!m->queue && hipMalloc(&m->queue, 256) != hipSuccess) {
         (void)hipGetLastError();
         return fail(RK_ENOMEM, "cannot allocate the work queue");
@@ -710,6 +716,7 @@ int radau_integrate(rk_mech *m, int64_t n, double dt, const double *yin, double 
     if ((variant == 1 || variant == 2) && !group_ok)
         return fail(RK_EINVAL, "radau_integrate: the wave and mixed variants need K + 1 <= 56");
     int rc = ensure_workspace(m, std::max<int64_t>(n, 1));
+    if (rc == RK_OK && variant == 0) rc = ensure_lane_scratch(m, n);
     if (rc != RK_OK) return rc;
     hipStream_t st = static_cast<hipStream_t>(stream);
     rk::RadauParams p{};
@@ -805,7 +812,8 @@ static int dbg_common(rk_mech *m, int64_t n, const void *a, const void *b) {
     if (n < 0) return fail(RK_EINVAL, "n < 0");
     if (n > 0 && (!a || !b || !is_device_ptr(a) || !is_device_ptr(b)))
         return fail(RK_EINVAL, "arrays must be device memory");
-    return ensure_workspace(m, std::max<int64_t>(n, 1));
+    const int rc = ensure_workspace(m, std::max<int64_t>(n, 1));
+    return rc != RK_OK ? rc : ensure_lane_scratch(m, n);
 }
 
 int rk_dbg_rhs(rk_mech *m, int64_t n, const double *y, double *f, void *stream) {

@@ -35,20 +35,48 @@ __device__ __forceinline__ float gelu_grad(float x) {
     return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * 0.39894228040143268f * expf(-0.5f * x * x);
 }
 
-// Z = X W^T + b (pre-activation), A = act(Z); tile: 64 outputs x 4 rows per block
+// Z = X W^T + b (pre-activation), A = act(Z) on the matrix cores: each
+// wavefront computes a 16 (rows of X) x 16 (outputs) tile with
+// v_mfma_f32_16x16x4_f32, k in steps of 4.  The BF16 weights are exact in
+// FP32, so the products are BF16 weight x FP32 activation, accumulated in
+// FP32.  Operand layout of the 16x16x4 FP32 MFMA (lane l = 16 q + i):
+// A[i][q] and B[q][i] in, D[4 q + v][i] (v = 0..3) out.  A block of four
+// wavefronts covers 16 rows x 64 outputs; din and dout need not be
+// multiples of 4 or 16 (out-of-range operands are zero, results not stored).
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 __global__ __launch_bounds__(256) void layer_fwd_kernel(int64_t B, int din, int dout, const float *__restrict__ X,
                                                         const uint16_t *__restrict__ Wb, const float *__restrict__ bias,
                                                         float *__restrict__ Z, float *__restrict__ A, int act) {
-    const int o = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int64_t b = (int64_t)blockIdx.y * 4 + (threadIdx.x >> 6);
-    if (o >= dout || b >= B) return;
-    const float *x = X + b * din;
-    const uint16_t *w = Wb + (size_t)o * din;
-    float acc = 0.0f;
-    for (int i = 0; i < din; ++i) acc += x[i] * __builtin_bit_cast(float, (uint32_t)w[i] << 16);
-    acc += bias[o];
-    Z[b * dout + o] = acc;
-    if (A) A[b * dout + o] = act ? gelu(acc) : acc;
+    const int lane = threadIdx.x & 63;
+    const int i = lane & 15, q = lane >> 4;
+    const int o0 = blockIdx.x * 64 + (threadIdx.x >> 6) * 16;
+    const int64_t b0 = (int64_t)blockIdx.y * 16;
+    if (o0 >= dout) return;                       // whole wavefront: no MFMA with partial exec
+    const int64_t row = b0 + i;                    // A operand: X[row][k + q]
+    const int oc = o0 + i;                         // B operand: W[oc][k + q]
+    const bool rok = row < B, ook = oc < dout;
+    const float *x = X + (rok ? row : 0) * din;
+    const uint16_t *w = Wb + (size_t)(ook ? oc : 0) * din;
+    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int k = 0; k < din; k += 4) {
+        const int kk = k + q;
+        const float a = (rok && kk < din) ? x[kk] : 0.0f;
+        const float b = (ook && kk < din) ? __builtin_bit_cast(float, (uint32_t)w[kk] << 16) : 0.0f;
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+    }
+    // this lane holds D[4 q + v][i]: rows b0 + 4 q + v, output o0 + i
+    if (!ook) return;
+    const float bo = bias[oc];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int64_t r = b0 + 4 * q + v;
+        if (r < B) {
+            const float zz = acc[v] + bo;
+            Z[r * dout + oc] = zz;
+            if (A) A[r * dout + oc] = act ? gelu(zz) : zz;
+        }
+    }
 }
 
 // dZ = dA * act'(Z) (in place on dA when act)
@@ -208,7 +236,8 @@ hipError_t Mlp::forward(int64_t B, const float *x, hipStream_t st) {
     for (size_t l = 0; l + 1 < L; ++l) {
         const int din = dims[l], dout = dims[l + 1];
         const bool hidden = l + 2 < L;
-        hipLaunchKernelGGL(layer_fwd_kernel, dim3(blocks(dout, 64), blocks(B, 4)), dim3(256), 0, st, B, din, dout, in,
+        if (blocks(B, 16) > 0x7fffffffu) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(layer_fwd_kernel, dim3(blocks(dout, 64), blocks(B, 16)), dim3(256), 0, st, B, din, dout, in,
                            wbf + off, params + off + (int64_t)dout * din, pre[l + 1], hidden ? acts[l + 1] : nullptr,
                            hidden ? 1 : 0);
         in = acts[l + 1];

@@ -1,0 +1,95 @@
+"""GPU parity on the 150-species mechanism (N = 151).  It runs on the
+lane-per-state kernel (the cooperative kernels hold at most 56 unknowns), so
+the batches are small; same bar as the other mechanisms: max relative error
+<= 1e-5 on T and on every Y_i whose oracle value exceeds 1e-8."""
+import numpy as np
+import pytest
+
+from paper_1607_03884_amd import configs, gen
+from tests.parity import banner, integration_errors, rhs_magnitudes, EPS
+
+pytestmark = pytest.mark.gpu
+
+K = 150
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch, torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def m150_path():
+    return configs.mech_path("M150")
+
+
+@pytest.fixture(scope="module")
+def g150(torch_dev, m150_path):
+    from paper_1607_03884_amd import Mechanism
+    return Mechanism(m150_path)
+
+
+@pytest.fixture(scope="module")
+def o150(oracle_mod, m150_path):
+    return oracle_mod.Mech(m150_path)
+
+
+def _dev(torch_dev, rows):
+    torch, dev = torch_dev
+    return torch.from_numpy(gen.to_soa(rows)).to(dev)
+
+
+def test_m150_rhs_jacobian(torch_dev, g150, o150):
+    banner("M150 source terms and Jacobian")
+    mech = gen.make_mechanism(configs.MECHS["M150"])
+    rows = configs.states_for(configs.WORKLOADS["cfg4"], 24)
+    y = _dev(torch_dev, rows)
+    f = g150.dbg_rhs(y).cpu().numpy().T
+    J = g150.dbg_jacobian(y).cpu().numpy().T.reshape(len(rows), K + 1, K + 1)
+    worst = 0.0
+    for row, fg, Jg in zip(rows, f, J):
+        fr = o150.rhs(row[:K + 1], row[-1])
+        mag = rhs_magnitudes(mech, o150, row)
+        assert np.all(np.abs(fg - fr) <= 2000 * EPS * mag + 1e-300)
+        Jr = o150.jac(row[:K + 1], row[-1])
+        scale = np.abs(Jr).max(axis=1, keepdims=True) + 1e-300
+        worst = max(worst, float((np.abs(Jg - Jr) / scale).max()))
+    assert worst <= 1e-11, worst
+
+
+@pytest.mark.parametrize("dt", [1e-6, 1e-4])
+def test_m150_lane_parity(torch_dev, g150, o150, dt):
+    """The first five PaSR-like M150 states (burnt ones, 25-55 steps each) over
+    each global step, lane kernel.  The lane kernel keeps its N x N matrices
+    in global memory, so each elimination step waits on memory: a state
+    costs seconds, which bounds the batch of this test."""
+    torch, _ = torch_dev
+    banner(f"M150 cfg4 5 states dt={dt} lane")
+    rows = configs.states_for(configs.WORKLOADS["cfg4"], 5)
+    g150.set_option("variant", "lane")
+    out = g150.integrate(_dev(torch_dev, rows), dt, configs.ATOL, configs.RTOL)
+    torch.cuda.synchronize()
+    st = g150.stats(per_state=True)
+    got = out.cpu().numpy().T
+    ref, res = o150.integrate(rows, dt)
+    assert np.all(res["status"] == 0) and np.all(st["per_state_status"] == 0)
+    eT, eY = integration_errors(got, ref, K)
+    same = np.mean(st["per_state_steps"] == res["nstep"])
+    print(f"M150 lane: kernel {st['kernel_ms']:.1f} ms, steps/state {st['steps'] / len(rows):.1f}, "
+          f"max rel err T {eT:.2e} Y {eY:.2e}, identical step counts {same:.4f}")
+    assert eT <= 1e-5 and eY <= 1e-5
+    assert np.abs(got[:, 1:K + 1].sum(1) - rows[:, 1:K + 1].sum(1)).max() <= 1e-12
+
+
+def test_m150_group_variants_refused(torch_dev, g150):
+    """The cooperative variants refuse N = 151 with an error instead of running."""
+    banner("M150 group variants refused")
+    from paper_1607_03884_amd._lib import RkError
+    rows = configs.states_for(configs.WORKLOADS["cfg4"], 4)
+    for v in ("wave", "mixed"):
+        g150.set_option("variant", v)
+        with pytest.raises(RkError):
+            g150.integrate(_dev(torch_dev, rows), 1e-6)
+    g150.set_option("variant", "auto")
