@@ -22,6 +22,7 @@ warm-up and one timed step each for the comparison block.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -86,6 +87,8 @@ def main() -> int:
                     help="other forms timed (1 warm-up + 1 step each) for the comparison block")
     ap.add_argument("--cpu-sample", type=int, default=16384)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--dt", type=float, default=None,
+                    help="only this global step size (profiling runs; the headline uses every dt)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after timing, run one plain 512 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -103,6 +106,11 @@ def main() -> int:
     from paper_1607_03884_amd.flops import Costs
 
     wl = configs.WORKLOADS[args.workload]
+    if args.dt is not None:
+        if not any(abs(args.dt - d) <= 1e-12 * d for d in wl.dts):
+            print(f"--dt must be one of {wl.dts}", file=sys.stderr)
+            return 2
+        wl = dataclasses.replace(wl, dts=(args.dt,))
     path = configs.mech_path(wl.mech)
     mech_def = gen.make_mechanism(configs.MECHS[wl.mech])
     costs = Costs.of(mech_def)

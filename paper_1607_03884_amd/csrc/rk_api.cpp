@@ -251,6 +251,7 @@ int upload(rk_mech *m, const std::vector<Rx> &rx, const std::vector<double> &alo
     char *b = static_cast<char *>(m->dev_block);
     rk::DevMech &d = m->dev;
     d.K = K; d.R = R; d.N = K + 1; d.n3b = m->n3b;
+    d.nsp = m->sp_off[K];
     d.W = reinterpret_cast<const double *>(b + parts[0].off);
     d.invW = reinterpret_cast<const double *>(b + parts[1].off);
     d.Tmid = reinterpret_cast<const double *>(b + parts[2].off);
@@ -529,7 +530,7 @@ hipError_t launch_integrator(rk_mech *m, const rk::RadauParams &p, int64_t n, co
     }
     m->last_nbins = nbins;
     if (variant == 1 || variant == 2) {
-        if (m->group_blocks == 0) m->group_blocks = rk::group_max_blocks(m->K + 1, m->R);
+        if (m->group_blocks == 0) m->group_blocks = rk::group_max_blocks(m->dev);
         const int spb = rk::group_states_per_block(m->K + 1);
         const int64_t need = (n + spb - 1) / spb;
         const int64_t cap = std::max<int64_t>(1, (int64_t)m->group_blocks * gpct / 100);
@@ -711,7 +712,7 @@ int radau_integrate(rk_mech *m, int64_t n, double dt, const double *yin, double 
     if (n > 0 && (!yin || !yout)) return fail(RK_EINVAL, "radau_integrate: NULL state pointer");
     if (n > 0 && (!is_device_ptr(yin) || !is_device_ptr(yout)))
         return fail(RK_EINVAL, "radau_integrate: state arrays must be device memory");
-    const bool group_ok = rk::group_supported(m->K + 1) && rk::group_lds_bytes(m->K + 1, m->R) <= 65536;
+    const bool group_ok = rk::group_supported(m->K + 1) && rk::group_lds_bytes(m->dev) <= 65536;
     const int variant = m->variant >= 0 ? m->variant : (group_ok ? 1 : 0);
     if ((variant == 1 || variant == 2) && !group_ok)
         return fail(RK_EINVAL, "radau_integrate: the wave and mixed variants need K + 1 <= 56");

@@ -65,10 +65,11 @@ int group_states_per_block(int N) {
     return g.G ? kWave / g.G : 0;
 }
 
-size_t group_lds_bytes(int N, int R) {
-    const GroupShape g = group_shape(N);
+size_t group_lds_bytes(const DevMech &m) {
+    const GroupShape g = group_shape(m.N);
     if (!g.G) return 0;
-    return (size_t)(kWave / g.G) * group_lds_doubles(g.NC, R) * sizeof(double);
+    const size_t slices = (size_t)(kWave / g.G) * group_lds_doubles(g.NC, m.R) * sizeof(double);
+    return slices + shared_tables(g.G, m.K, m.nsp, m.n3b).bytes;
 }
 
 hipError_t launch_radau_group(const DevMech &m, const RadauParams &p, int64_t n, const double *yin, double *yout,
@@ -88,10 +89,10 @@ hipError_t launch_radau_group(const DevMech &m, const RadauParams &p, int64_t n,
     return launch_shape(g, false, m, p, n, yin, yout, counters, queue + 2, fb_list, queue + 1, nullptr, grid, st);
 }
 
-int group_max_blocks(int N, int R) {
-    const GroupShape g = group_shape(N);
+int group_max_blocks(const DevMech &m) {
+    const GroupShape g = group_shape(m.N);
     if (!g.G) return 1;
-    const size_t lds = group_lds_bytes(N, R);
+    const size_t lds = group_lds_bytes(m);
     const int per_cu = g.G == 16 ? occupancy_group16(g.NC, lds) : occupancy_group64(g.NC, lds);
     int dev = 0, cus = 0;
     (void)hipGetDevice(&dev);

@@ -116,6 +116,12 @@ struct GL {
     double *hist;     // h of the last accepted step, its error, h of the last step, pressure, time
     double *f0s;      // f(y0) of the current step, [NC]
     int *ctr;         // rarely read per-state counters (lane 0 updates them)
+    // mechanism tables read inside loops, staged in block-shared LDS: the
+    // species -> reaction lists (entry = reaction << 4 | (nu + 8)) always,
+    // the collision efficiencies for 16-lane groups (global memory otherwise)
+    const int *spoff;
+    const int *sprx;
+    const double *eff;
 };
 
 // per-state counters kept in LDS
@@ -125,6 +131,27 @@ __host__ __device__ constexpr int rec_chunk(int R) { return R < 64 ? R : 64; }
 
 __host__ __device__ constexpr int group_lds_doubles(int NC, int R) {
     return 3 * NC + 8 * rec_chunk(R) + NC * (NC + 1) + 2 * NC + NC + 3 * NC + 5 + NC + (K_NCTR + 1) / 2;
+}
+
+// Block-shared LDS copies of mechanism tables (after the group slices): the
+// packed species -> reaction lists, and for 16-lane groups (small
+// mechanisms, four groups per block) the collision efficiencies.
+struct SharedTables {
+    int off_spoff, off_sprx, off_eff, bytes;
+};
+
+__host__ __device__ inline SharedTables shared_tables(int G, int K, int nsp, int n3b) {
+    SharedTables t;
+    t.off_spoff = 0;
+    t.off_sprx = (K + 1) * 4;
+    t.off_eff = ((t.off_sprx + nsp * 4) + 7) / 8 * 8;
+    t.bytes = t.off_eff + (G == 16 ? n3b * K * 8 : 0);
+    return t;
+}
+
+template <int G, int NC>
+__host__ __device__ inline size_t block_lds_bytes(int K, int R, int nsp, int n3b) {
+    return (size_t)(kWave / G) * group_lds_doubles(NC, R) * sizeof(double) + shared_tables(G, K, nsp, n3b).bytes;
 }
 
 template <int NC>
@@ -181,7 +208,8 @@ __device__ __forceinline__ RxEval eval_reaction(const DevMech &m, const GL &L, i
     double dlnkf = (p[P_B] + p[P_EAR] * invT) * invT;
     double Mc = 0.0, dlnkf_dM = 0.0;
     if (e.kind != 0) {
-        const double *ef = m.eff + (size_t)((info >> 12) - 1) * K;
+        const double *ef = L.eff + (size_t)((info >> 12) - 1) * K;
+#pragma unroll 4
         for (int k = 0; k < K; ++k) Mc += ef[k] * L.C[k];
     }
     if (e.kind == 2) {
@@ -271,8 +299,8 @@ __device__ __forceinline__ double rhs_g(const DevMech &m, const GL &L, int r, do
     const Mix x = mixture<G>(m, L, r, yv, P, th);
     const int R = m.R, CH = rec_chunk(R);
     double wdot = 0.0;
-    int i = x.isY ? m.sp_off[x.k] : 0;
-    const int iend = x.isY ? m.sp_off[x.k + 1] : 0;
+    int i = x.isY ? L.spoff[x.k] : 0;
+    const int iend = x.isY ? L.spoff[x.k + 1] : 0;
     for (int j0 = 0; j0 < R; j0 += CH) {
         const int j1 = min(R, j0 + CH);
         for (int j = j0 + r; j < j1; j += G) {
@@ -283,9 +311,9 @@ __device__ __forceinline__ double rhs_g(const DevMech &m, const GL &L, int r, do
         }
         sync_wave();
         for (; i < iend; ++i) {
-            const int2 e = m.sp_rx[i];
-            if (e.x >= j1) break;
-            wdot += e.y * L.rec[e.x - j0];
+            const int e = L.sprx[i], jr = e >> 4;
+            if (jr >= j1) break;
+            wdot += ((e & 15) - 8) * L.rec[jr - j0];
         }
         sync_wave();
     }
@@ -305,8 +333,8 @@ __device__ __forceinline__ void jac_g(const DevMech &m, const GL &L, int r, doub
     const double T = x.T, invT = x.invT, rho = x.rho, Wbar = x.Wbar;
     for (int i = r; i < NC * LD; i += G) L.J[i] = 0.0;
     double wdot = 0.0, dwdT = 0.0, sS = 0.0;
-    int i = x.isY ? m.sp_off[x.k] : 0;
-    const int iend = x.isY ? m.sp_off[x.k + 1] : 0;
+    int i = x.isY ? L.spoff[x.k] : 0;
+    const int iend = x.isY ? L.spoff[x.k + 1] : 0;
     for (int j0 = 0; j0 < R; j0 += CH) {
         const int j1 = min(R, j0 + CH);
         // per-reaction records: q, dq/dT|C, S, dense coefficient, 4 mass-action partials
@@ -342,7 +370,7 @@ __device__ __forceinline__ void jac_g(const DevMech &m, const GL &L, int r, doub
                 if (mm == sp.y) dq += rc[5];
                 if (mm == sp.z) dq += rc[6];
                 if (mm == sp.w) dq += rc[7];
-                if (info & 15) dq += rc[3] * m.eff[(size_t)((info >> 12) - 1) * K + mm];
+                if (info & 15) dq += rc[3] * L.eff[(size_t)((info >> 12) - 1) * K + mm];
                 if (dq != 0.0) {
                     L.J[(1 + sp.x) * LD + r] -= dq;
                     if (sp.y >= 0) L.J[(1 + sp.y) * LD + r] -= dq;
@@ -353,12 +381,12 @@ __device__ __forceinline__ void jac_g(const DevMech &m, const GL &L, int r, doub
         }
         // species sums over this chunk, in reaction order
         for (; i < iend; ++i) {
-            const int2 e = m.sp_rx[i];
-            if (e.x >= j1) break;
-            const double *rc = L.rec + 8 * (e.x - j0);
-            wdot += e.y * rc[0];
-            dwdT += e.y * rc[1];
-            sS += e.y * rc[2];
+            const int e = L.sprx[i], jr = e >> 4, nu = (e & 15) - 8;
+            if (jr >= j1) break;
+            const double *rc = L.rec + 8 * (jr - j0);
+            wdot += nu * rc[0];
+            dwdT += nu * rc[1];
+            sS += nu * rc[2];
         }
         sync_wave();
     }
@@ -666,7 +694,29 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(G == 16 ? 2 
     const int r = threadIdx.x & (G - 1);
     const int grp = threadIdx.x / G;
     const int N = m.N, K = m.K;
-    const GL L = group_lds<NC>(smem + (size_t)grp * group_lds_doubles(NC, m.R), m.R);
+    GL L = group_lds<NC>(smem + (size_t)grp * group_lds_doubles(NC, m.R), m.R);
+    {
+        // stage the species lists (and, for 16-lane groups, the efficiencies) once per block
+        const SharedTables tb = shared_tables(G, K, m.nsp, m.n3b);
+        char *sh = reinterpret_cast<char *>(smem + (size_t)(kWave / G) * group_lds_doubles(NC, m.R));
+        int *so = reinterpret_cast<int *>(sh + tb.off_spoff);
+        int *sx = reinterpret_cast<int *>(sh + tb.off_sprx);
+        for (int i = threadIdx.x; i <= K; i += kWave) so[i] = m.sp_off[i];
+        for (int i = threadIdx.x; i < m.nsp; i += kWave) {
+            const int2 e = m.sp_rx[i];
+            sx[i] = (e.x << 4) | (e.y + 8);
+        }
+        L.spoff = so;
+        L.sprx = sx;
+        if constexpr (G == 16) {
+            double *se = reinterpret_cast<double *>(sh + tb.off_eff);
+            for (int i = threadIdx.x; i < m.n3b * K; i += kWave) se[i] = m.eff[i];
+            L.eff = se;
+        } else {
+            L.eff = m.eff;
+        }
+        sync_wave();
+    }
     const bool comp = r < N;                       // lane holds a state component
     const double dt = rp.dt, atol = rp.atol, rtol = rp.rtol, kappa = rp.kappa;
     const int kmax = rp.kmax;
@@ -1032,7 +1082,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(G == 16 ? 2 
 template <typename S, int G, int NC>
 void launch_one(const DevMech &m, const RadauParams &p, int64_t n, const double *yin, double *yout, int32_t *cnt,
                 int *queue, const int *order, const int *work_n, const double *pred, int grid, hipStream_t st) {
-    const size_t lds = (size_t)(kWave / G) * group_lds_doubles(NC, m.R) * sizeof(double);
+    const size_t lds = block_lds_bytes<G, NC>(m.K, m.R, m.nsp, m.n3b);
     hipLaunchKernelGGL((radau_group_kernel<S, G, NC>), dim3(grid), dim3(kWave), lds, st, m, p, n, yin, yout, cnt, queue,
                        order, work_n, pred);
 }

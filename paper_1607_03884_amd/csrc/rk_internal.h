@@ -22,6 +22,7 @@ enum RPar { P_A = 0, P_B, P_EAR, P_A0, P_B0, P_EA0R, P_TA, P_T3, P_T1, P_T2, P_D
 // wavefront-uniform indices, so the loads are scalar (constant cache).
 struct DevMech {
     int K, R, N, n3b;
+    int nsp;               // entries of sp_rx
     const double *W;       // [K]  kg/mol
     const double *invW;    // [K]
     const double *Tmid;    // [K]
@@ -82,7 +83,7 @@ int group_states_per_block(int N);
 hipError_t launch_radau_group(const DevMech &m, const RadauParams &p, int64_t n, const double *yin, double *yout,
                               int32_t *counters, int *queue, int *fb_list, const int *order, const double *pred,
                               bool mixed, int grid, hipStream_t st);
-int group_max_blocks(int N, int R);
+int group_max_blocks(const DevMech &m);
 // per-family entry points (rk_group16.hip, rk_group64.hip): NC = register columns
 hipError_t launch_group16(int NC, bool fp32, const DevMech &m, const RadauParams &p, int64_t n, const double *yin,
                           double *yout, int32_t *cnt, int *queue, const int *order, const int *work_n,
@@ -93,7 +94,7 @@ hipError_t launch_group64(int NC, bool fp32, const DevMech &m, const RadauParams
 int occupancy_group16(int NC, size_t lds);
 int occupancy_group64(int NC, size_t lds);
 hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t st);
-size_t group_lds_bytes(int N, int R);
+size_t group_lds_bytes(const DevMech &m);   // per block
 
 // Predictor network (rk_mlp.hip): FP32 masters, BF16 copy used in products.
 struct Mlp {
