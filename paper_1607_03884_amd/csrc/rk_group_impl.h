@@ -115,6 +115,7 @@ struct GL {
     double *zs;       // previous step's stage values, [3][NC] (parked here, not in registers)
     double *hist;     // h of the last accepted step, its error, h of the last step, pressure, time
     double *f0s;      // f(y0) of the current step, [NC]
+    double *q;        // net rates of all reactions (source terms): the record chunk when R <= 64
     int *ctr;         // rarely read per-state counters (lane 0 updates them)
     // mechanism tables read inside loops, staged in block-shared LDS: the
     // species -> reaction lists (entry = reaction << 4 | (nu + 8)) always,
@@ -130,7 +131,8 @@ enum { K_NREJ = 0, K_NNEWT, K_NNF, K_NFEV, K_NJEV, K_NLU, K_NCTR };
 __host__ __device__ constexpr int rec_chunk(int R) { return R < 64 ? R : 64; }
 
 __host__ __device__ constexpr int group_lds_doubles(int NC, int R) {
-    return 3 * NC + 8 * rec_chunk(R) + NC * (NC + 1) + 2 * NC + NC + 3 * NC + 5 + NC + (K_NCTR + 1) / 2;
+    return 3 * NC + 8 * rec_chunk(R) + NC * (NC + 1) + 2 * NC + NC + 3 * NC + 5 + NC + (K_NCTR + 1) / 2 +
+           (R > 64 ? R : 0);
 }
 
 // Block-shared LDS copies of mechanism tables (after the group slices): the
@@ -168,6 +170,7 @@ __device__ __forceinline__ GL group_lds(double *base, int R) {
     L.hist = L.zs + 3 * NC;
     L.f0s = L.hist + 5;
     L.ctr = reinterpret_cast<int *>(L.f0s + NC);
+    L.q = R > 64 ? L.f0s + NC + (K_NCTR + 1) / 2 : L.rec;
     return L;
 }
 
@@ -297,26 +300,24 @@ template <int G>
 __device__ __forceinline__ double rhs_g(const DevMech &m, const GL &L, int r, double yv, double P) {
     Thermo th;
     const Mix x = mixture<G>(m, L, r, yv, P, th);
-    const int R = m.R, CH = rec_chunk(R);
-    double wdot = 0.0;
-    int i = x.isY ? L.spoff[x.k] : 0;
-    const int iend = x.isY ? L.spoff[x.k + 1] : 0;
-    for (int j0 = 0; j0 < R; j0 += CH) {
-        const int j1 = min(R, j0 + CH);
-        for (int j = j0 + r; j < j1; j += G) {
-            const RxEval e = eval_reaction(m, L, j, x.T, x.lnT, x.invT, x.lnPRT, false);
-            double q = e.kf * e.Pf - e.kr * e.Pp;
-            if (e.kind == 1) q *= e.Mc;
-            L.rec[j - j0] = q;
-        }
-        sync_wave();
-        for (; i < iend; ++i) {
-            const int e = L.sprx[i], jr = e >> 4;
-            if (jr >= j1) break;
-            wdot += ((e & 15) - 8) * L.rec[jr - j0];
-        }
-        sync_wave();
+    const int R = m.R;
+    // all reaction rates first (no barrier between rounds, so the loads of
+    // one round overlap the arithmetic of the previous), then each species
+    // lane sums its list in reaction order
+    for (int j = r; j < R; j += G) {
+        const RxEval e = eval_reaction(m, L, j, x.T, x.lnT, x.invT, x.lnPRT, false);
+        double q = e.kf * e.Pf - e.kr * e.Pp;
+        if (e.kind == 1) q *= e.Mc;
+        L.q[j] = q;
     }
+    sync_wave();
+    double wdot = 0.0;
+    const int iend = x.isY ? L.spoff[x.k + 1] : 0;
+    for (int i = x.isY ? L.spoff[x.k] : 0; i < iend; ++i) {
+        const int e = L.sprx[i];
+        wdot += ((e & 15) - 8) * L.q[e >> 4];
+    }
+    sync_wave();
     const double hw = gsum<G>(x.isY ? th.h * wdot : 0.0);
     const double cpm = gsum<G>(x.isY ? x.Y * th.cp * x.invW : 0.0);
     if (r == 0) return -hw * x.T / (x.rho * cpm);
