@@ -108,32 +108,40 @@ int radau_integrate(rk_mech *mech, int64_t n_states, double dt, const double *d_
 int stats_get(rk_mech *mech, rk_stats *out, int32_t *per_state_steps, int32_t *per_state_status);
 
 /* radau_set_option — integrator options of a handle (strings):
- *   "variant"  "auto" (default: "wave" when K + 1 <= 16, else "lane") |
- *              "lane" (one lane per state, the paper's per-thread pattern) |
- *              "wave" (16 lanes of a wavefront cooperate on one state, the
- *              paper's per-block pattern; persistent work queue; K + 1 <= 16) |
+ *   "variant"  "auto" (default: "wave" when K + 1 <= 56, else "lane") |
+ *              "lane" (one lane per state, the paper's per-thread pattern;
+ *              any K; the matrices live in global memory, so large
+ *              mechanisms are slow) |
+ *              "wave" (a group of lanes cooperates on one state, the paper's
+ *              per-block pattern: 16 lanes for K + 1 <= 16, a whole wavefront
+ *              for K + 1 <= 56; LU factors in registers; persistent work
+ *              queue) |
  *              "mixed" (as "wave" with the iteration matrices equilibrated and
- *              factored in FP32; source terms, residuals, error estimate
- *              (plus one FP64-residual refinement) and control in FP64; a
- *              state whose Newton iteration diverges twice in a row after
- *              its first accepted step is
- *              re-integrated from its initial value with FP64 factors)
+ *              factored in FP32; every solve takes one refinement step
+ *              against the FP64 matrices; source terms, residuals, error
+ *              estimate and control in FP64; a state whose Newton iteration
+ *              diverges twice in a row after its first accepted step is
+ *              re-integrated from its initial value with FP64 factors).
+ *              "wave" and "mixed" return RK_EINVAL for K + 1 > 56.
  *   "binning"  number of cost bins (0..64, default 0): one source-term
  *              evaluation per state gives the key ||dt f(y0)|| (RMS in the
  *              error weights); states are queued costliest bin first
  *   "grid_pct" share of the resident capacity launched for the persistent
  *              kernels (10..100, default 100)
  *   "autotune" "1": on the first call per dt, time the integrator on the first
- *              min(n, 32768) states for bins in {0, 8, 16, 32} and grid in
+ *              min(n, 32768) states (8192 for K + 1 > 16) for bins in
+ *              {0, 8, 16, 32} and grid in
  *              {100 %, 50 %}, keep the fastest (this call blocks the host);
  *              "0": forget the choices
  *   "predictor" path of a predictor file (network widths K+2 -> ... -> 3(K+1)+2,
  *              standardisation, parameters) trained for one global step size;
  *              calls with that dt and the "wave" or "mixed" variant start each
- *              state's first step from the predicted step size and stage
- *              values and keep them only if Newton converges, else restart the
- *              state cold; with "binning" the bin key becomes the predicted
- *              step count.  "none" removes all predictors.
+ *              state's first step from the predicted step size (rounded to dt
+ *              times a power of two) and stage values and keep them only if
+ *              Newton converges on that attempt, else restart the state
+ *              exactly as a cold start; with "binning" (or "autotune") the
+ *              bin key becomes the predicted step count.  A file for another
+ *              K is refused (RK_EINVAL).  "none" removes all predictors.
  *   "predictor_use" "both" (default) | "h0" (predicted first step size only,
  *              stage values start at zero) | "z0" (predicted stage values with
  *              the default first step size): ablations of the predictor
@@ -163,7 +171,8 @@ int rk_dbg_jacobian(rk_mech *mech, int64_t n, const double *d_y, double *d_J, vo
  * masters used as BF16 (round-to-nearest-even) in every product, with FP32
  * accumulation.  Flat parameter order: per layer W [d_out][d_in] row-major,
  * then b [d_out].  Device arrays (d_*) are row-major [B][width] float32.
- * Loss: sum_b mask_b sum_o w_o (y_bo - t_bo)^2 * inv_count. */
+ * Loss: sum_b mask_b sum_o w_o (y_bo - t_bo)^2 * inv_count.  The forward
+ * pass runs on the matrix cores (FP32 MFMA with the BF16-valued weights). */
 typedef struct rk_mlp rk_mlp;
 
 /* rk_mlp_create — allocate a network on the current device (2..8 widths,
