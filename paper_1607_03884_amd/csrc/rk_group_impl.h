@@ -362,9 +362,20 @@ __device__ __forceinline__ void jac_g(const DevMech &m, const GL &L, int r, doub
         // Mkm = sum_j nu_kj dq_j/dC_m into the Y block; lane r owns column r (species r-1)
         if (x.isY) {
             const int mm = x.k;
+            // the reaction tables are read-only and indexed uniformly here: read
+            // them through the constant address space so the loads go to the
+            // scalar cache (through a generic pointer they become vector loads,
+            // since the kernel also writes global memory)
+            typedef const __attribute__((address_space(4))) int cint;
+            cint *rspc = (cint *)m.rsp;       // 4 ints per reaction
+            cint *rinfoc = (cint *)m.rinfo;
             for (int j = j0; j < j1; ++j) {
-                const int4 sp = m.rsp[j];
-                const int info = m.rinfo[j];
+                int4 sp;
+                sp.x = rspc[4 * j];
+                sp.y = rspc[4 * j + 1];
+                sp.z = rspc[4 * j + 2];
+                sp.w = rspc[4 * j + 3];
+                const int info = rinfoc[j];
                 const double *rc = L.rec + 8 * (j - j0);
                 double dq = 0.0;
                 if (mm == sp.x) dq += rc[4];
@@ -415,7 +426,8 @@ __device__ __forceinline__ void jac_g(const DevMech &m, const GL &L, int r, doub
         const double a = Wbar * (fk - Wk * sS / rho);
         double *row = L.J + r * LD;
         row[0] = Wk / rho * (dwdT - sS * invT) + fk * invT;
-        for (int c = 1; c <= K; ++c) row[c] = (Wk * row[c] + a) * m.invW[c - 1];
+        const __attribute__((address_space(4))) double *iw = (const __attribute__((address_space(4))) double *)m.invW;
+        for (int c = 1; c <= K; ++c) row[c] = (Wk * row[c] + a) * iw[c - 1];
     }
     sync_wave();
 }
