@@ -61,7 +61,8 @@ typedef struct rk_stats {
     int64_t d_hist32[20];
     double d_mean64, d_mean32;
     double kernel_ms;         /* device time of the last call (HIP events) */
-    int64_t fp32_fallback;    /* states the mixed variant re-ran with FP64 factors */
+    int64_t fp32_fallback;    /* states the mixed variant re-ran with FP64 factors
+                                 (block variant: switched to FP64-accurate solves) */
     int32_t nbins_used;       /* cost bins of the work queue (0: input order) */
     int32_t grid_used;        /* blocks launched for the integrator */
     int64_t predictor_kept;     /* states whose predicted first step converged */
@@ -108,7 +109,8 @@ int radau_integrate(rk_mech *mech, int64_t n_states, double dt, const double *d_
 int stats_get(rk_mech *mech, rk_stats *out, int32_t *per_state_steps, int32_t *per_state_status);
 
 /* radau_set_option — integrator options of a handle (strings):
- *   "variant"  "auto" (default: "wave" when K + 1 <= 56, else "lane") |
+ *   "variant"  "auto" (default: "wave" when K + 1 <= 56, "block" when
+ *              K + 1 <= 153, else "lane") |
  *              "lane" (one lane per state, the paper's per-thread pattern;
  *              any K; the matrices live in global memory, so large
  *              mechanisms are slow) |
@@ -123,6 +125,16 @@ int stats_get(rk_mech *mech, rk_stats *out, int32_t *per_state_steps, int32_t *p
  *              diverges twice in a row after its first accepted step is
  *              re-integrated from its initial value with FP64 factors).
  *              "wave" and "mixed" return RK_EINVAL for K + 1 > 56.
+ *              "block" (57 <= K + 1 <= 153, R <= 2048: a block of 512 lanes
+ *              cooperates on one state, the per-block pattern for large
+ *              mechanisms (Sec. 1.2, Sec. 4); iteration matrices equilibrated
+ *              and factored in FP32 in registers, three lanes per row, J in
+ *              FP64 in device memory; one refinement step per solve against
+ *              the FP64 matrices; a state whose Newton iteration diverges twice
+ *              in a row after its first accepted step continues with three
+ *              refinement steps per solve (FP64-accurate solves) and counts
+ *              in fp32_fallback; no predictor; persistent work queue).
+ *              RK_EINVAL outside those sizes.
  *   "binning"  number of cost bins (0..64, default 0): one source-term
  *              evaluation per state gives the key ||dt f(y0)|| (RMS in the
  *              error weights); states are queued costliest bin first

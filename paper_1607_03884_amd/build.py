@@ -6,8 +6,11 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["rk_api.cpp", "rk_kernels.hip", "rk_group.hip", "rk_group16.hip", "rk_group64.hip", "rk_mlp.hip",
-           "rk_pred.hip"]
+SOURCES = ["rk_api.cpp", "rk_kernels.hip", "rk_group.hip", "rk_group16.hip", "rk_group64.hip", "rk_block.hip",
+           "rk_mlp.hip", "rk_pred.hip"]
+# per-source extra flags: the block kernel's elimination loops (51 register
+# columns, nested) must unroll completely so every register index is constant
+EXTRA_FLAGS = {"rk_block.hip": ["-mllvm", "-pragma-unroll-threshold=400000"]}
 OUT = os.path.join(HERE, "librkchem.so")
 
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -26,7 +29,7 @@ def build_library(verbose: bool = False, csrc: str = CSRC, out: str = OUT) -> st
     procs = []
     for s in SOURCES:
         obj = os.path.join(objdir, s + f".{os.getpid()}.o")
-        cmd = [hipcc] + compile_flags + ["-c", os.path.join(csrc, s), "-o", obj]
+        cmd = [hipcc] + compile_flags + EXTRA_FLAGS.get(s, []) + ["-c", os.path.join(csrc, s), "-o", obj]
         procs.append((s, obj, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)))
     objs, errors = [], []
     for s, obj, p in procs:

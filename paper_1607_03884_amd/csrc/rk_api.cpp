@@ -363,6 +363,21 @@ int ensure_lane_scratch(rk_mech *m, int64_t n) {
     return RK_OK;
 }
 
+// Jacobian slabs of the block kernel, one per resident block
+int ensure_block_slab(rk_mech *m) {
+    if (m->block_blocks == 0) m->block_blocks = rk::block_max_blocks(m->dev);
+    const size_t need = rk::block_slab_doubles(m->K + 1, m->block_blocks);
+    if (need > m->block_slab_cap) {
+        if (m->block_slab) { (void)hipDeviceSynchronize(); (void)hipFree(m->block_slab); m->block_slab = nullptr; m->block_slab_cap = 0; }
+        if (hipMalloc(&m->block_slab, need * sizeof(double)) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(RK_ENOMEM, "cannot allocate the block-kernel Jacobian slabs");
+        }
+        m->block_slab_cap = need;
+    }
+    return RK_OK;
+}
+
 int ensure_workspace(rk_mech *m, int64_t n) {
     if (!m->queue && hipMalloc(&m->queue, 256) != hipSuccess) {
         (void)hipGetLastError();
@@ -529,6 +544,13 @@ hipError_t launch_integrator(rk_mech *m, const rk::RadauParams &p, int64_t n, co
         order = m->order;
     }
     m->last_nbins = nbins;
+    if (variant == 3) {
+        // one block per state; the slabs were sized for block_blocks blocks
+        const int64_t cap = std::max<int64_t>(1, (int64_t)m->block_blocks * gpct / 100);
+        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(n, cap));
+        m->last_grid = grid;
+        return rk::launch_radau_block(m->dev, p, n, yin, yout, m->counters, m->queue, order, m->block_slab, grid, st);
+    }
     if (variant == 1 || variant == 2) {
         if (m->group_blocks == 0) m->group_blocks = rk::group_max_blocks(m->dev);
         const int spb = rk::group_states_per_block(m->K + 1);
@@ -625,6 +647,7 @@ void mech_free(rk_mech *m) {
     if (m->counters) (void)hipFree(m->counters);
     if (m->queue) (void)hipFree(m->queue);
     if (m->fb_list) (void)hipFree(m->fb_list);
+    if (m->block_slab) (void)hipFree(m->block_slab);
     if (m->bins) (void)hipFree(m->bins);
     if (m->order) (void)hipFree(m->order);
     if (m->hist) (void)hipFree(m->hist);
@@ -651,6 +674,7 @@ int radau_set_option(rk_mech *m, const char *key, const char *value) {
         if (v == "lane") m->variant = 0;
         else if (v == "wave") m->variant = 1;
         else if (v == "mixed") m->variant = 2;
+        else if (v == "block") m->variant = 3;
         else if (v == "auto") m->variant = -1;
         else return fail(RK_EINVAL, "unknown variant " + v);
         return RK_OK;
@@ -713,11 +737,15 @@ int radau_integrate(rk_mech *m, int64_t n, double dt, const double *yin, double 
     if (n > 0 && (!is_device_ptr(yin) || !is_device_ptr(yout)))
         return fail(RK_EINVAL, "radau_integrate: state arrays must be device memory");
     const bool group_ok = rk::group_supported(m->K + 1) && rk::group_lds_bytes(m->dev) <= 65536;
-    const int variant = m->variant >= 0 ? m->variant : (group_ok ? 1 : 0);
+    const bool block_ok = rk::block_supported(m->K + 1) && rk::block_lds_bytes(m->R) <= 65536;
+    const int variant = m->variant >= 0 ? m->variant : (group_ok ? 1 : (block_ok ? 3 : 0));
     if ((variant == 1 || variant == 2) && !group_ok)
         return fail(RK_EINVAL, "radau_integrate: the wave and mixed variants need K + 1 <= 56");
+    if (variant == 3 && !block_ok)
+        return fail(RK_EINVAL, "radau_integrate: the block variant needs 57 <= K + 1 <= 153 and R <= 2048");
     int rc = ensure_workspace(m, std::max<int64_t>(n, 1));
     if (rc == RK_OK && variant == 0) rc = ensure_lane_scratch(m, n);
+    if (rc == RK_OK && variant == 3) rc = ensure_block_slab(m);
     if (rc != RK_OK) return rc;
     hipStream_t st = static_cast<hipStream_t>(stream);
     rk::RadauParams p{};
@@ -731,7 +759,7 @@ int radau_integrate(rk_mech *m, int64_t n, double dt, const double *yin, double 
     p.kappa = m->kappa > 0.0 ? m->kappa : std::max(10.0 * 2.220446049250313e-16 / rtol, std::min(0.03, std::sqrt(rtol)));
     p.h0 = m->h0 > 0.0 ? m->h0 : std::min(dt, 1e-6);
     int nbins = m->nbins, gpct = m->grid_pct;
-    if (m->autotune && n >= 4096) {
+    if (m->autotune && n >= 4096 && variant != 3) {   // block kernel: trials would cost seconds each
         int rc2 = autotune(m, n, dt, yin, atol, rtol, st, p, variant, nbins, gpct);
         if (rc2 != RK_OK) return rc2;
     }

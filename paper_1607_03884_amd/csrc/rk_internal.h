@@ -94,6 +94,14 @@ hipError_t launch_group64(int NC, bool fp32, const DevMech &m, const RadauParams
 int occupancy_group16(int NC, size_t lds);
 int occupancy_group64(int NC, size_t lds);
 hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t st);
+// block-cooperative variant (rk_block.hip): one 512-lane block per state,
+// FP32 factors in registers, J in a per-block slab of global memory
+bool block_supported(int N);
+size_t block_lds_bytes(int R);
+size_t block_slab_doubles(int N, int grid);
+int block_max_blocks(const DevMech &m);
+hipError_t launch_radau_block(const DevMech &m, const RadauParams &p, int64_t n, const double *yin, double *yout,
+                              int32_t *counters, int *queue, const int *order, double *slab, int grid, hipStream_t st);
 size_t group_lds_bytes(const DevMech &m);   // per block
 
 // Predictor network (rk_mlp.hip): FP32 masters, BF16 copy used in products.
@@ -151,7 +159,7 @@ struct rk_mech {
     void *dev_block = nullptr;
     int device = 0;
     // options
-    int variant = -1;          // -1 auto, 0 lane, 1 wave (16-lane groups), 2 mixed (FP32 factors)
+    int variant = -1;          // -1 auto, 0 lane, 1 wave, 2 mixed (FP32 factors), 3 block (N > 56)
     int kmax = 7, nmax = 100000;
     double kappa = 0.0, h0 = 0.0;
     // workspace of the last call
@@ -177,6 +185,9 @@ struct rk_mech {
     int last_nbins = 0, last_grid = 0;
     std::vector<rk::Predictor *> predictors;   // one per global step size
     int group_blocks = 0;      // resident blocks of the group kernel (cached)
+    int block_blocks = 0;      // resident blocks of the block kernel (cached)
+    double *block_slab = nullptr;   // per-block Jacobian slabs of the block kernel
+    size_t block_slab_cap = 0;      // doubles
     int64_t last_n = 0;
     hipStream_t last_stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
