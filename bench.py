@@ -16,6 +16,8 @@ Forms (same library, same inputs):
   learned_mixed  learned with FP32 iteration-matrix factors (FP64 residuals)
   mixed          binned with FP32 factors
   lane           one state per lane (the paper's per-thread pattern)
+  block          one 512-lane block per state, FP32 factors (N = 57..153;
+                 the only cooperative form for the 150-species workload)
 The headline form (--form) is timed over --steps steps; the others get one
 warm-up and one timed step each for the comparison block.
 """
@@ -35,6 +37,7 @@ if ROOT not in sys.path:
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CUs x 64 FP64 FMA/clk x 2 flops x 2.4 GHz
 
 KERNEL_SOURCES = {"radau_group_kernel": ["rk_group_impl.h", "rk_group16.hip", "rk_internal.h"],
+                  "radau_block_kernel": ["rk_block.hip", "rk_group_impl.h", "rk_internal.h"],
                   "radau_lane_kernel": ["rk_kernels.hip", "rk_internal.h"]}
 
 FORMS = {
@@ -44,6 +47,7 @@ FORMS = {
     "learned_mixed": dict(variant="mixed", binning=0, autotune=1, predictor=True),
     "mixed": dict(variant="mixed", binning=0, autotune=1, predictor=False),
     "lane": dict(variant="lane", binning=0, autotune=0, predictor=False),
+    "block": dict(variant="block", binning=0, autotune=0, predictor=False),
 }
 
 
@@ -89,6 +93,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--dt", type=float, default=None,
                     help="only this global step size (profiling runs; the headline uses every dt)")
+    ap.add_argument("--n-states", type=int, default=None,
+                    help="only the first N states of the workload (a bounded sample of a large workload)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after timing, run one plain 512 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -115,6 +121,8 @@ def main() -> int:
     mech_def = gen.make_mechanism(configs.MECHS[wl.mech])
     costs = Costs.of(mech_def)
     states = configs.states_for(wl)
+    if args.n_states is not None:
+        states = states[:max(1, args.n_states)]
     n = len(states)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -161,6 +169,9 @@ def main() -> int:
                         "fp64_frac": tf / FP64_VECTOR_PEAK_TFLOPS}
 
     form = args.form
+    if configs.MECHS[wl.mech].n_species + 1 > 56 and FORMS[form]["variant"] in ("wave", "mixed"):
+        print(f"[bench] {wl.mech} has more than 56 unknowns: headline form 'block'", flush=True)
+        form = "block"
     if FORMS[form]["predictor"] and not have_pred:
         print(f"[bench] no predictor files for {wl.mech}; headline form falls back to 'binned'", flush=True)
         form = "binned"
@@ -204,7 +215,8 @@ def main() -> int:
         tot_ms += kernel_ms[dt]
         per_dt[f"{dt:g}"] = rec
     achieved = tot_flops / (tot_ms * 1e-3) / 1e12
-    kname = "radau_lane_kernel" if FORMS[form]["variant"] == "lane" else "radau_group_kernel"
+    kname = {"lane": "radau_lane_kernel", "block": "radau_block_kernel"}.get(FORMS[form]["variant"],
+                                                                             "radau_group_kernel")
     roofline = {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": measured_traffic(kname, wl.name),
                 "kernel": kname, "flops_per_launch": tot_flops / len(wl.dts),
@@ -276,11 +288,12 @@ def main() -> int:
         "ms_per_step": sec_per_step * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"{wl.name}: synthetic {wl.mech} ({mech.K} species, {mech.R} reversible reactions), "
-                               f"{n} PaSR-like states, one global step at each of {list(wl.dts)} s",
+                               f"{n} PaSR-like states" + (f" (first {n} of {wl.n_states})" if n < wl.n_states else "")
+                               + f", one global step at each of {list(wl.dts)} s",
                    "n_states": n, "dts": list(wl.dts), "atol": configs.ATOL, "rtol": configs.RTOL,
                    "form": form, "variant": fdesc["variant"], "autotune": fdesc["autotune"],
                    "predictor": fdesc["predictor"],
-                   "factors": "FP32 (FP64 residuals)" if fdesc["variant"] == "mixed" else "FP64"},
+                   "factors": "FP32 (FP64 residuals)" if fdesc["variant"] in ("mixed", "block") else "FP64"},
         "per_dt": per_dt,
         "compare": compare,
         "roofline": roofline,
