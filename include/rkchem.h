@@ -125,7 +125,8 @@ int stats_get(rk_mech *mech, rk_stats *out, int32_t *per_state_steps, int32_t *p
  *              diverges twice in a row after its first accepted step is
  *              re-integrated from its initial value with FP64 factors).
  *              "wave" and "mixed" return RK_EINVAL for K + 1 > 56.
- *              "block" (57 <= K + 1 <= 153, R <= 2048: a block of 512 lanes
+ *              "block" (57 <= K + 1 <= 153, R + third-body rows up to about
+ *              2000: a block of 512 lanes
  *              cooperates on one state, the per-block pattern for large
  *              mechanisms (Sec. 1.2, Sec. 4); iteration matrices equilibrated
  *              and factored in FP32 in registers, three lanes per row, J in

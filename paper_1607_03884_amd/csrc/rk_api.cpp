@@ -737,12 +737,12 @@ int radau_integrate(rk_mech *m, int64_t n, double dt, const double *yin, double 
     if (n > 0 && (!is_device_ptr(yin) || !is_device_ptr(yout)))
         return fail(RK_EINVAL, "radau_integrate: state arrays must be device memory");
     const bool group_ok = rk::group_supported(m->K + 1) && rk::group_lds_bytes(m->dev) <= 65536;
-    const bool block_ok = rk::block_supported(m->K + 1) && rk::block_lds_bytes(m->R) <= 65536;
+    const bool block_ok = rk::block_supported(m->K + 1) && rk::block_lds_bytes(m->dev) <= 163840;
     const int variant = m->variant >= 0 ? m->variant : (group_ok ? 1 : (block_ok ? 3 : 0));
     if ((variant == 1 || variant == 2) && !group_ok)
         return fail(RK_EINVAL, "radau_integrate: the wave and mixed variants need K + 1 <= 56");
     if (variant == 3 && !block_ok)
-        return fail(RK_EINVAL, "radau_integrate: the block variant needs 57 <= K + 1 <= 153 and R <= 2048");
+        return fail(RK_EINVAL, "radau_integrate: the block variant needs 57 <= K + 1 <= 153 and at most 160 KB of LDS per block");
     int rc = ensure_workspace(m, std::max<int64_t>(n, 1));
     if (rc == RK_OK && variant == 0) rc = ensure_lane_scratch(m, n);
     if (rc == RK_OK && variant == 3) rc = ensure_block_slab(m);

@@ -40,20 +40,21 @@ constexpr int BP = 3;           // lanes per matrix row
 constexpr int BRP = 170;        // rows per part: lane t = part * BRP + row
 constexpr int NPB = 176;        // padded vector length in LDS
 constexpr int kCW = 51;         // register columns per part (N <= 153)
-constexpr int BCH = 256;        // reactions per Jacobian record chunk
+constexpr int BCH = 192;        // reactions per Jacobian record chunk
 
 // LDS of one block, offsets in doubles.  The matrix-vector product reuses the
 // substitution relay for its input vector.
 struct BlockLds {
-    int C, h, s, q, red, key, bci, hist, ctr, svec, yb, xb, relay, scr, zs, f0s, col, prow, total;
+    int C, h, s, Mc, q, red, key, bci, hist, ctr, svec, yb, xb, relay, scr, zs, f0s, col, prow, e1, total;
 };
 
-__host__ __device__ inline BlockLds block_layout(int R) {
+__host__ __device__ inline BlockLds block_layout(int R, int n3b, int N) {
     BlockLds b{};
     int o = 0;
     b.C = o; o += NPB;
     b.h = o; o += NPB;
     b.s = o; o += NPB;
+    b.Mc = o; o += (n3b + 7) / 8 * 8;             // third-body concentration of every efficiency row
     b.q = o; o += (R > 8 * BCH ? R : 8 * BCH);   // reaction rates, or Jacobian records
     b.red = o; o += 32;                            // 2 phases x 2 values x 8 wavefronts
     b.key = o; o += 32;                            // 2 buffers x 2 keys x 8 wavefronts
@@ -69,23 +70,26 @@ __host__ __device__ inline BlockLds block_layout(int R) {
     b.f0s = o; o += NPB;
     b.col = o; o += 3 * NPB;                       // floats: 2 buffers x 3 arrays x NPB
     b.prow = o; o += 3 * NPB;                      // floats: 2 buffers x 3 arrays x NPB
+    b.e1 = o; o += (N * BP * kCW + 1) / 2;          // floats: factors of E1, column-major (ld N)
     b.total = o;
     return b;
 }
 
 struct BL {
-    double *C, *h, *s, *q, *red, *hist, *svec, *yb, *xb, *relay, *scr, *zs, *f0s;
+    double *C, *h, *s, *Mc, *q, *red, *hist, *svec, *yb, *xb, *relay, *scr, *zs, *f0s;
     uint64_t *key;
     int *bci, *ctr;
     float *col, *prow;
+    float *e1;        // E1 and its factors: entry (row, c) at e1[c * N + row]
 };
 
-__device__ __forceinline__ BL block_lds(double *base, int R) {
-    const BlockLds o = block_layout(R);
+__device__ __forceinline__ BL block_lds(double *base, int R, int n3b, int N) {
+    const BlockLds o = block_layout(R, n3b, N);
     BL L;
     L.C = base + o.C;
     L.h = base + o.h;
     L.s = base + o.s;
+    L.Mc = base + o.Mc;
     L.q = base + o.q;
     L.red = base + o.red;
     L.key = reinterpret_cast<uint64_t *>(base + o.key);
@@ -101,6 +105,7 @@ __device__ __forceinline__ BL block_lds(double *base, int R) {
     L.f0s = base + o.f0s;
     L.col = reinterpret_cast<float *>(base + o.col);
     L.prow = reinterpret_cast<float *>(base + o.prow);
+    L.e1 = reinterpret_cast<float *>(base + o.e1);
     return L;
 }
 
@@ -154,25 +159,86 @@ __device__ __forceinline__ MixB mixture_b(const DevMech &m, const BL &L, int t, 
         th = Thermo{0.0, 0.0, 0.0, 0.0};
     }
     __syncthreads();
+    // [M] of every efficiency row, once per evaluation: wavefront w takes rows
+    // w, w + 8, ...; its lanes read the row coalesced and reduce in a fixed order
+    const int w = wave_of(t), ln = t & 63, K = m.K;
+    for (int b = w; b < m.n3b; b += 8) {
+        const double *er = m.eff + (size_t)b * K;
+        double acc = 0.0;
+        for (int k = ln; k < K; k += 64) acc += er[k] * L.C[k];
+        acc = gsum<64>(acc);
+        if (ln == 0) L.Mc[b] = acc;
+    }
+    __syncthreads();
     return x;
 }
 
-__device__ __forceinline__ GL rx_view(const DevMech &m, const BL &L) {
-    GL g{};
-    g.C = L.C;
-    g.h = L.h;
-    g.s = L.s;
-    g.eff = m.eff;
-    return g;
+// Per-reaction quantities (as eval_reaction of the wavefront kernels, with
+// the third-body concentration taken from the per-row values in LDS)
+__device__ __forceinline__ RxEval eval_reaction_b(const DevMech &m, const BL &L, int j, double T, double lnT,
+                                                  double invT, double lnPRT, bool derivs) {
+    RxEval e;
+    e.sp = m.rsp[j];
+    const int info = m.rinfo[j];
+    const double *p = m.rpar + (size_t)j * P_NPAR;
+    e.kind = info & 15;
+    e.nr = (info >> 4) & 15;
+    e.np = (info >> 8) & 15;
+    double kf = p[P_A] * exp(p[P_B] * lnT - p[P_EAR] * invT);
+    double dlnkf = (p[P_B] + p[P_EAR] * invT) * invT;
+    double Mc = 0.0, dlnkf_dM = 0.0;
+    if (e.kind != 0) Mc = L.Mc[(info >> 12) - 1];
+    if (e.kind == 2) {
+        const double k0 = p[P_A0] * exp(p[P_B0] * lnT - p[P_EA0R] * invT);
+        const double Pr = k0 * Mc / kf;
+        const double ta = p[P_TA], t3 = p[P_T3], t1 = p[P_T1], t2 = p[P_T2];
+        const double e3 = exp(-T / t3), e1 = exp(-T / t1), e2 = exp(-t2 * invT);
+        const double Fc = (1.0 - ta) * e3 + ta * e1 + e2;
+        const double lF = log10(Fc);
+        const double c = -0.4 - 0.67 * lF, nn = 0.75 - 1.27 * lF;
+        const double xx = log10(Pr) + c;
+        const double den = nn - 0.14 * xx;
+        const double f1 = xx / den, g1 = 1.0 + f1 * f1;
+        if (derivs) {
+            const double dlnk0 = (p[P_B0] + p[P_EA0R] * invT) * invT;
+            const double dlnPr = dlnk0 - dlnkf;
+            const double dFc = -(1.0 - ta) / t3 * e3 - ta / t1 * e1 + t2 * invT * invT * e2;
+            const double dlF = dFc / (Fc * M_LN10);
+            const double dxT = dlnPr / M_LN10 - 0.67 * dlF, dnT = -1.27 * dlF;
+            const double df1T = (nn * dxT - xx * dnT) / (den * den);
+            const double dl10F_T = dlF / g1 - 2.0 * lF * f1 * df1T / (g1 * g1);
+            const double df1M = nn / (Mc * M_LN10) / (den * den);
+            const double dl10F_M = -2.0 * lF * f1 * df1M / (g1 * g1);
+            dlnkf = dlnkf + dlnPr / (1.0 + Pr) + M_LN10 * dl10F_T;
+            dlnkf_dM = 1.0 / (Mc * (1.0 + Pr)) + M_LN10 * dl10F_M;
+        }
+        kf = kf * (Pr / (1.0 + Pr)) * exp10(lF / g1);
+    }
+    const int4 sp = e.sp;
+    double dS = L.s[sp.z] - L.s[sp.x];
+    double dH = L.h[sp.z] - L.h[sp.x];
+    double Pf = L.C[sp.x], Pp = L.C[sp.z];
+    if (sp.y >= 0) { dS -= L.s[sp.y]; dH -= L.h[sp.y]; Pf *= L.C[sp.y]; }
+    if (sp.w >= 0) { dS += L.s[sp.w]; dH += L.h[sp.w]; Pp *= L.C[sp.w]; }
+    const double dnu = p[P_DNU];
+    const double Kc = exp(dS - dH + dnu * lnPRT);
+    e.kf = kf;
+    e.kr = kf / Kc;
+    e.dlnkf = dlnkf;
+    e.dlnkf_dM = dlnkf_dM;
+    e.dlnKc = (dH - dnu) * invT;
+    e.Mc = Mc;
+    e.Pf = Pf;
+    e.Pp = Pp;
+    return e;
 }
 
 // f(y): component t in lane t (0 beyond N)
 __device__ __forceinline__ double rhs_b(const DevMech &m, const BL &L, int t, double yv, double P, int &ph) {
     Thermo th;
     const MixB x = mixture_b(m, L, t, yv, P, th, ph);
-    const GL g = rx_view(m, L);
     for (int j = t; j < m.R; j += BT) {
-        const RxEval e = eval_reaction(m, g, j, x.T, x.lnT, x.invT, x.lnPRT, false);
+        const RxEval e = eval_reaction_b(m, L, j, x.T, x.lnT, x.invT, x.lnPRT, false);
         double q = e.kf * e.Pf - e.kr * e.Pp;
         if (e.kind == 1) q *= e.Mc;
         L.q[j] = q;
@@ -193,14 +259,15 @@ __device__ __forceinline__ double rhs_b(const DevMech &m, const BL &L, int t, do
 }
 
 // Jacobian into the slab JS (column-major, leading dimension LDJ): lane t
-// accumulates column t (species t - 1) over the reactions, then owns row t
+// accumulates column t (species t - 1) over the reactions with non-returning
+// atomic adds (the lane's own column, so the adds land in program order and
+// the result is deterministic; no round trip per update), then owns row t
 // for the final species-row pass.
 __device__ __forceinline__ void jac_b(const DevMech &m, const BL &L, int t, double yv, double P, double *JS, int LDJ,
                                       int &ph) {
     const int K = m.K, R = m.R, N = m.N;
     Thermo th;
     const MixB x = mixture_b(m, L, t, yv, P, th, ph);
-    const GL g = rx_view(m, L);
     const double T = x.T, invT = x.invT, rho = x.rho, Wbar = x.Wbar;
     for (int i = t; i < N * LDJ; i += BT) JS[i] = 0.0;
     __syncthreads();
@@ -212,7 +279,7 @@ __device__ __forceinline__ void jac_b(const DevMech &m, const BL &L, int t, doub
     for (int j0 = 0; j0 < R; j0 += BCH) {
         const int j1 = min(R, j0 + BCH);
         for (int j = j0 + t; j < j1; j += BT) {
-            const RxEval e = eval_reaction(m, g, j, T, x.lnT, invT, x.lnPRT, true);
+            const RxEval e = eval_reaction_b(m, L, j, T, x.lnT, invT, x.lnPRT, true);
             const double Rj = e.kf * e.Pf - e.kr * e.Pp;
             const double dRdT = Rj * e.dlnkf + e.kr * e.Pp * e.dlnKc;
             const double sMA = e.kind == 1 ? e.Mc : 1.0;
@@ -251,10 +318,10 @@ __device__ __forceinline__ void jac_b(const DevMech &m, const BL &L, int t, doub
                 if (mm == sp.w) dq += rc[7];
                 if (info & 15) dq += rc[3] * m.eff[(size_t)((info >> 12) - 1) * K + mm];
                 if (dq != 0.0) {
-                    col[1 + sp.x] -= dq;
-                    if (sp.y >= 0) col[1 + sp.y] -= dq;
-                    col[1 + sp.z] += dq;
-                    if (sp.w >= 0) col[1 + sp.w] += dq;
+                    unsafeAtomicAdd(col + 1 + sp.x, -dq);
+                    if (sp.y >= 0) unsafeAtomicAdd(col + 1 + sp.y, -dq);
+                    unsafeAtomicAdd(col + 1 + sp.z, dq);
+                    if (sp.w >= 0) unsafeAtomicAdd(col + 1 + sp.w, dq);
                 }
             }
         }
@@ -293,20 +360,24 @@ __device__ __forceinline__ void jac_b(const DevMech &m, const BL &L, int t, doub
         const double a = Wbar * (fk - Wk * sS / rho);
         JS[t] = Wk / rho * (dwdT - sS * invT) + fk * invT;
         const __attribute__((address_space(4))) double *iw = (const __attribute__((address_space(4))) double *)m.invW;
-        for (int c = 1; c <= K; ++c) {
-            double *e = JS + (size_t)c * LDJ + t;
-            *e = (Wk * *e + a) * iw[c - 1];
+        // batches of 16 columns: all loads of a batch issue before its stores
+        for (int c0 = 1; c0 <= K; c0 += 16) {
+            double v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) v[u] = c0 + u <= K ? JS[(size_t)(c0 + u) * LDJ + t] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 16; ++u)
+                if (c0 + u <= K) JS[(size_t)(c0 + u) * LDJ + t] = (Wk * v[u] + a) * iw[c0 + u - 1];
         }
     }
     __syncthreads();
 }
 
-// FP32 factors of one row segment of E1 and E2 (equilibrated), the lane's
-// elimination positions and, for the lane that holds its row's pivot entry,
-// the reciprocal of that entry
+// FP32 factors of one row segment of E2 (equilibrated; those of E1 are in
+// LDS), the lane's elimination positions and, for the lane that holds its
+// row's pivot entry, the reciprocal of that entry
 template <int CW>
 struct BLU {
-    float a[CW];
     float re[CW], im[CW];
     int pos1, pos2;
     double d1, d2r, d2i;
@@ -328,6 +399,7 @@ __device__ __forceinline__ void form_factor(BLU<CW> &F, const BL &L, const doubl
     const int t = threadIdx.x;
     double m1 = 0.0, m2 = 0.0;
     const double iscr = active ? 1.0 / L.svec[row] : 0.0;
+    float *e1 = L.e1 + (active ? row : 0);      // this row of E1: entry c at e1[c * N]
 #pragma unroll
     for (int j = 0; j < CW; ++j) {
         const int c = part * CW + j;
@@ -337,7 +409,7 @@ __device__ __forceinline__ void form_factor(BLU<CW> &F, const BL &L, const doubl
         const double v1 = ((c == row ? gh : 0.0) - jv) * w, v2 = ((c == row ? ah : 0.0) - jv) * w;
         m1 = fmax(m1, fabs(v1));
         m2 = fmax(m2, fabs(v2));
-        F.a[j] = (float)v1;
+        if (active) e1[(size_t)c * N] = (float)v1;
         F.re[j] = (float)v2;
     }
     m2 = fmax(m2, bh);   // imaginary part: diagonal only (scale 1 there)
@@ -357,7 +429,7 @@ __device__ __forceinline__ void form_factor(BLU<CW> &F, const BL &L, const doubl
 #pragma unroll
     for (int j = 0; j < CW; ++j) {
         const int c = part * CW + j;
-        F.a[j] *= f1;
+        if (active) e1[(size_t)c * N] *= f1;
         F.re[j] *= f2;
         F.im[j] = (float)((active && c == row) ? bh * i2 : 0.0);
     }
@@ -380,11 +452,11 @@ __device__ __forceinline__ void form_factor(BLU<CW> &F, const BL &L, const doubl
                 // pivot candidates: this column of every row, keys of the unused rows
                 uint64_t k1 = 0, k2 = 0;
                 if (mine) {
-                    const float xr = F.re[c], xi = F.im[c];
-                    cb[row] = F.a[c];
+                    const float xr = F.re[c], xi = F.im[c], xa = e1[(size_t)k * N];
+                    cb[row] = xa;
                     cb[NPB + row] = xr;
                     cb[2 * NPB + row] = xi;
-                    if (!u1) k1 = pkey(fabs((double)F.a[c]), row);
+                    if (!u1) k1 = pkey(fabs((double)xa), row);
                     if (!u2) k2 = pkey((double)xr * xr + (double)xi * xi, row);
                 }
                 k1 = gmaxu<64>(k1);
@@ -407,8 +479,8 @@ __device__ __forceinline__ void form_factor(BLU<CW> &F, const BL &L, const doubl
                     u1 = true;
                     F.pos1 = k;
 #pragma unroll
-                    for (int j = 0; j < CW; ++j) pb[part * CW + j] = F.a[j];
-                    if (part == pk) F.d1 = 1.0 / (double)F.a[c];
+                    for (int j = 0; j < CW; ++j) pb[part * CW + j] = e1[(size_t)(part * CW + j) * N];
+                    if (part == pk) F.d1 = 1.0 / (double)cb[row];
                 }
                 if (active && row == p2) {
                     u2 = true;
@@ -435,26 +507,42 @@ __device__ __forceinline__ void form_factor(BLU<CW> &F, const BL &L, const doubl
                     lr = xr * ir - xi * ii;
                     li = xr * ii + xi * ir;
                 }
-                if (mine && !u1) F.a[c] = l1;
+                if (mine && !u1) e1[(size_t)k * N] = l1;
                 if (mine && !u2) {
                     F.re[c] = lr;
                     F.im[c] = li;
                 }
                 __syncthreads();
-                // elimination of the unused rows (columns after k)
-                if (!u1 && part >= pk) {
-#pragma unroll
-                    for (int j = 0; j < CW; ++j)
-                        if (j > c || part > pk) F.a[j] -= l1 * pb[part * CW + j];
-                }
+                // elimination of the unused rows (columns after k): E2 in
+                // registers, then E1 in LDS in batches of 8 columns whose loads
+                // all issue before the batch's stores
                 if (!u2 && part >= pk) {
 #pragma unroll
                     for (int j = 0; j < CW; ++j)
                         if (j > c || part > pk) {
                             const float ur = pb[NPB + part * CW + j], ui = pb[2 * NPB + part * CW + j];
-                            F.re[j] -= lr * ur - li * ui;
-                            F.im[j] -= lr * ui + li * ur;
+                            F.re[j] = fmaf(-lr, ur, fmaf(li, ui, F.re[j]));
+                            F.im[j] = fmaf(-lr, ui, fmaf(-li, ur, F.im[j]));
                         }
+                }
+                if (!u1 && part >= pk) {
+                    constexpr int UB = 8;
+#pragma unroll
+                    for (int j0 = 0; j0 < CW; j0 += UB) {
+                        float ev[UB], pv[UB];
+#pragma unroll
+                        for (int u = 0; u < UB; ++u) {
+                            const int j = j0 + u;
+                            const bool on = j < CW && (j > c || part > pk);
+                            ev[u] = on ? e1[(size_t)(part * CW + j) * N] : 0.0f;
+                            pv[u] = on ? pb[part * CW + j] : 0.0f;
+                        }
+#pragma unroll
+                        for (int u = 0; u < UB; ++u) {
+                            const int j = j0 + u;
+                            if (j < CW && (j > c || part > pk)) e1[(size_t)(part * CW + j) * N] = fmaf(-l1, pv[u], ev[u]);
+                        }
+                    }
                 }
                 buf ^= 1;
             }
@@ -486,6 +574,7 @@ __device__ __forceinline__ void bsolve(const BLU<CW> &F, const BL &L, int part, 
     double *y1 = L.yb, *yr = L.yb + NPB, *yi = L.yb + 2 * NPB;
     double *x1 = L.xb, *xr = L.xb + NPB, *xi = L.xb + 2 * NPB;
     double *r1 = L.relay, *rr = L.relay + NPB, *ri = L.relay + 2 * NPB;
+    const float *e1r = L.e1 + (active ? row : 0);
     for (int pk = 0; pk < BP; ++pk) {
         if (pk > 0) {
             if (active && part == pk - 1) { r1[row] = a1; rr[row] = ar; ri[row] = ai; }
@@ -499,8 +588,9 @@ __device__ __forceinline__ void bsolve(const BLU<CW> &F, const BL &L, int part, 
             if (k < N) {
                 if (mine && F.pos1 == k) y1[k] = a1;
                 if (two && mine && F.pos2 == k) { yr[k] = ar; yi[k] = ai; }
+                const float lk = mine ? e1r[(size_t)k * N] : 0.0f;
                 __syncthreads();
-                if (mine && F.pos1 > k) a1 -= wd(F.a[c]) * y1[k];
+                if (mine && F.pos1 > k) a1 -= (double)lk * y1[k];
                 if (two && mine && F.pos2 > k) {
                     const double lr = wd(F.re[c]), li = wd(F.im[c]), vr = yr[k], vi = yi[k];
                     ar -= lr * vr - li * vi;
@@ -532,8 +622,9 @@ __device__ __forceinline__ void bsolve(const BLU<CW> &F, const BL &L, int part, 
                     xr[k] = ar * F.d2r - ai * F.d2i;
                     xi[k] = ar * F.d2i + ai * F.d2r;
                 }
+                const float uk = mine ? e1r[(size_t)k * N] : 0.0f;
                 __syncthreads();
-                if (mine && F.pos1 < k) a1 -= wd(F.a[c]) * x1[k];
+                if (mine && F.pos1 < k) a1 -= (double)uk * x1[k];
                 if (two && mine && F.pos2 < k) {
                     const double ur = wd(F.re[c]), ui = wd(F.im[c]), vr = xr[k], vi = xi[k];
                     ar -= ur * vr - ui * vi;
@@ -554,21 +645,35 @@ __device__ __forceinline__ void bsolve(const BLU<CW> &F, const BL &L, int part, 
 }
 
 // J v for up to three vectors (component r in lane r), FP64, from the slab
+template <int CW>
 __device__ __forceinline__ void bjv3(const BL &L, const double *JS, int LDJ, int part, int row, bool active, int N,
-                                     int CW, int nv, double &v1, double &v2, double &v3) {
+                                     int nv, double &v1, double &v2, double &v3) {
     const int t = threadIdx.x;
     double *vx = L.relay;
     if (t < N) { vx[t] = v1; vx[NPB + t] = v2; vx[2 * NPB + t] = v3; }
     __syncthreads();
     double s1 = 0.0, s2 = 0.0, s3 = 0.0;
     if (active) {
-        const int c0 = part * CW, c1 = min(N, c0 + CW);
-        for (int c = c0; c < c1; ++c) {
-            const double jv = JS[(size_t)c * LDJ + row];
-            s1 += jv * vx[c];
-            if (nv > 1) {
-                s2 += jv * vx[NPB + c];
-                s3 += jv * vx[2 * NPB + c];
+        // batches of 17 columns: the loads of a batch issue before its sums
+        constexpr int B = 17;
+#pragma unroll
+        for (int j0 = 0; j0 < CW; j0 += B) {
+            double jv[B];
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                const int c = part * CW + j0 + u;
+                jv[u] = (j0 + u < CW && c < N) ? JS[(size_t)c * LDJ + row] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                const int c = part * CW + j0 + u;
+                if (j0 + u < CW && c < N) {
+                    s1 += jv[u] * vx[c];
+                    if (nv > 1) {
+                        s2 += jv[u] * vx[NPB + c];
+                        s3 += jv[u] * vx[2 * NPB + c];
+                    }
+                }
             }
         }
         L.scr[(part * 3) * NPB + row] = s1;
@@ -597,7 +702,7 @@ __global__ __launch_bounds__(BT) void radau_block_kernel(DevMech m, RadauParams 
                                                          const int *__restrict__ order, double *__restrict__ slab,
                                                          int LDJ) {
     extern __shared__ double smem[];
-    const BL L = block_lds(smem, m.R);
+    const BL L = block_lds(smem, m.R, m.n3b, m.N);
     const int t = threadIdx.x, part = t / BRP, row = t - part * BRP;
     const int N = m.N, K = m.K;
     const bool active = part < BP && row < N, comp = t < N;
@@ -733,7 +838,7 @@ __global__ __launch_bounds__(BT) void radau_block_kernel(DevMech m, RadauParams 
                 for (int rf = 0; rf < nref; ++rf) {
                     // refinement against the FP64 matrices
                     double j1 = dW1, j2 = dW2, j3 = dW3;
-                    bjv3(L, JS, LDJ, part, row, active, N, CW, 3, j1, j2, j3);
+                    bjv3<CW>(L, JS, LDJ, part, row, active, N, 3, j1, j2, j3);
                     double q1 = comp ? b1 - (gh * dW1 - j1) : 0.0;
                     double q2 = comp ? b2 - ((ah * dW2 - j2) - bh * dW3) : 0.0;
                     double q3 = comp ? b3 - ((ah * dW3 - j3) + bh * dW2) : 0.0;
@@ -784,7 +889,7 @@ __global__ __launch_bounds__(BT) void radau_block_kernel(DevMech m, RadauParams 
                 bsolve<CW>(F, L, part, row, active, N, false, ev, u2, u3);
                 for (int rf = 0; rf < nref; ++rf) {
                     double j1 = ev, j2 = 0.0, j3 = 0.0;
-                    bjv3(L, JS, LDJ, part, row, active, N, CW, 1, j1, j2, j3);
+                    bjv3<CW>(L, JS, LDJ, part, row, active, N, 1, j1, j2, j3);
                     double q1 = comp ? v - (gh * ev - j1) : 0.0;
                     u2 = u3 = 0.0;
                     bsolve<CW>(F, L, part, row, active, N, false, q1, u2, u3);
@@ -802,7 +907,7 @@ __global__ __launch_bounds__(BT) void radau_block_kernel(DevMech m, RadauParams 
                     bsolve<CW>(F, L, part, row, active, N, false, ev, u2, u3);
                     for (int rf = 0; rf < nref; ++rf) {
                         double j1 = ev, j2 = 0.0, j3 = 0.0;
-                        bjv3(L, JS, LDJ, part, row, active, N, CW, 1, j1, j2, j3);
+                        bjv3<CW>(L, JS, LDJ, part, row, active, N, 1, j1, j2, j3);
                         double q1 = comp ? v - (gh * ev - j1) : 0.0;
                         u2 = u3 = 0.0;
                         bsolve<CW>(F, L, part, row, active, N, false, q1, u2, u3);
@@ -907,13 +1012,17 @@ bool block_supported(int N) { return N > 56 && N <= BP * kCW && N <= BRP; }
 
 int block_ldj(int N) { return N + (N & 1); }
 
-size_t block_lds_bytes(int R) { return (size_t)block_layout(R).total * sizeof(double); }
+size_t block_lds_bytes(const DevMech &m) { return (size_t)block_layout(m.R, m.n3b, m.N).total * sizeof(double); }
 
 size_t block_slab_doubles(int N, int grid) { return (size_t)grid * N * block_ldj(N); }
 
 int block_max_blocks(const DevMech &m) {
+    // more than 64 KB of LDS per block (E1 and its factors live there)
+    (void)hipFuncSetAttribute((const void *)radau_block_kernel<kCW>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)block_lds_bytes(m));
+    (void)hipGetLastError();
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, radau_block_kernel<kCW>, BT, block_lds_bytes(m.R)) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, radau_block_kernel<kCW>, BT, block_lds_bytes(m)) !=
             hipSuccess ||
         per_cu < 1)
         per_cu = 1;
@@ -928,7 +1037,7 @@ hipError_t launch_radau_block(const DevMech &m, const RadauParams &p, int64_t n,
     if (n == 0) return hipSuccess;
     if (!block_supported(m.N) || grid < 1) return hipErrorInvalidValue;
     hipLaunchKernelGGL(reset_block_queue_kernel, dim3(1), dim3(64), 0, st, queue);
-    hipLaunchKernelGGL((radau_block_kernel<kCW>), dim3(grid), dim3(BT), block_lds_bytes(m.R), st, m, p, n, yin, yout,
+    hipLaunchKernelGGL((radau_block_kernel<kCW>), dim3(grid), dim3(BT), block_lds_bytes(m), st, m, p, n, yin, yout,
                        counters, queue, order, slab, block_ldj(m.N));
     return hipGetLastError();
 }

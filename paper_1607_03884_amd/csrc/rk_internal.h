@@ -97,7 +97,7 @@ hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t st);
 // block-cooperative variant (rk_block.hip): one 512-lane block per state,
 // FP32 factors in registers, J in a per-block slab of global memory
 bool block_supported(int N);
-size_t block_lds_bytes(int R);
+size_t block_lds_bytes(const DevMech &m);
 size_t block_slab_doubles(int N, int grid);
 int block_max_blocks(const DevMech &m);
 hipError_t launch_radau_block(const DevMech &m, const RadauParams &p, int64_t n, const double *yin, double *yout,
