@@ -16,7 +16,7 @@ Forms (same library, same inputs):
   learned_mixed  learned with FP32 iteration-matrix factors (FP64 residuals)
   mixed          binned with FP32 factors
   lane           one state per lane (the paper's per-thread pattern)
-  block          one 512-lane block per state, FP32 factors (N = 57..153;
+  block          one 512-lane block per state, FP32 factors, 16 proxy cost bins (N = 57..153;
                  the only cooperative form for the 150-species workload)
 The headline form (--form) is timed over --steps steps; the others get one
 warm-up and one timed step each for the comparison block.
@@ -47,7 +47,7 @@ FORMS = {
     "learned_mixed": dict(variant="mixed", binning=0, autotune=1, predictor=True),
     "mixed": dict(variant="mixed", binning=0, autotune=1, predictor=False),
     "lane": dict(variant="lane", binning=0, autotune=0, predictor=False),
-    "block": dict(variant="block", binning=0, autotune=0, predictor=False),
+    "block": dict(variant="block", binning=16, autotune=0, predictor=False),
 }
 
 
