@@ -214,6 +214,7 @@ def main() -> int:
         tot_flops += fl["flops"]
         tot_ms += kernel_ms[dt]
         per_dt[f"{dt:g}"] = rec
+        print(f"[bench] statistics launch dt={dt:g} done", flush=True)
     achieved = tot_flops / (tot_ms * 1e-3) / 1e12
     kname = {"lane": "radau_lane_kernel", "block": "radau_block_kernel"}.get(FORMS[form]["variant"],
                                                                              "radau_group_kernel")
@@ -233,6 +234,7 @@ def main() -> int:
         mech.integrate(y, dt, configs.ATOL, configs.RTOL, y_out=out, stream=stream)
         host_out.copy_(out, non_blocking=True)
     torch.cuda.synchronize()
+    print("[bench] host-copy step done", flush=True)
     pcie = {"states_per_s": n * len(wl.dts) / (time.perf_counter() - p0),
             "note": "one step with H2D copy of y before and D2H copy of y_out after each dt (pinned host memory)"}
     del host_in, host_out

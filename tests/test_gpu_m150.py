@@ -116,7 +116,8 @@ def test_m150_block_parity(torch_dev, g150, o150, dt):
 def test_m150_block_edges(torch_dev, g150):
     """Empty batch; a non-finite state among good ones (status NONFINITE, its
     row copied, the others unaffected); results identical bit for bit when the
-    persistent grid shrinks to a tenth (the state-to-block mapping changes)."""
+    persistent grid shrinks to a tenth or cost bins reorder the queue (the
+    state-to-block mapping changes)."""
     torch, dev = torch_dev
     banner("M150 block edges")
     g150.set_option("variant", "block")
@@ -135,6 +136,12 @@ def test_m150_block_edges(torch_dev, g150):
     small = g150.integrate(_dev(torch_dev, rows), 1e-6).cpu().numpy()
     g150.set_option("grid_pct", "100")
     assert np.array_equal(ref, small)
+    # cost bins reorder the queue; every state's result stays the same bits
+    g150.set_option("binning", "8")
+    binned = g150.integrate(_dev(torch_dev, rows), 1e-6).cpu().numpy()
+    assert g150.stats()["nbins_used"] == 8
+    g150.set_option("binning", "0")
+    assert np.array_equal(ref, binned)
     assert np.array_equal(np.delete(out, 5, axis=0), np.delete(ref.T, 5, axis=0))
     g150.set_option("variant", "auto")
 
