@@ -41,6 +41,7 @@ constexpr int BRP = 170;        // rows per part: lane t = part * BRP + row
 constexpr int NPB = 176;        // padded vector length in LDS
 constexpr int kCW = 51;         // register columns per part (N <= 153)
 constexpr int BCH = 192;        // reactions per Jacobian record chunk
+constexpr int CWP = 52;         // part stride of the pivot-row buffers (16-byte segments)
 
 // LDS of one block, offsets in doubles.  The matrix-vector product reuses the
 // substitution relay for its input vector.
@@ -55,7 +56,7 @@ __host__ __device__ inline BlockLds block_layout(int R, int n3b, int N) {
     b.h = o; o += NPB;
     b.s = o; o += NPB;
     b.Mc = o; o += (n3b + 7) / 8 * 8;             // third-body concentration of every efficiency row
-    b.q = o; o += (R > 8 * BCH ? R : 8 * BCH);   // reaction rates, or Jacobian records
+    b.q = o; o += ((R > 8 * BCH ? R : 8 * BCH) + 1) / 2 * 2;   // reaction rates, or Jacobian records
     b.red = o; o += 32;                            // 2 phases x 2 values x 8 wavefronts
     b.key = o; o += 32;                            // 2 buffers x 2 keys x 8 wavefronts
     b.bci = o; o += 4;
@@ -69,7 +70,7 @@ __host__ __device__ inline BlockLds block_layout(int R, int n3b, int N) {
     b.zs = o; o += 3 * NPB;
     b.f0s = o; o += NPB;
     b.col = o; o += 3 * NPB;                       // floats: 2 buffers x 3 arrays x NPB
-    b.prow = o; o += 3 * NPB;                      // floats: 2 buffers x 3 arrays x NPB
+    b.prow = o; o += 3 * NPB;                      // floats: 2 buffers x 3 arrays x NPB (16-byte aligned)
     b.e1 = o; o += (N * BP * kCW + 1) / 2;          // floats: factors of E1, column-major (ld N)
     b.total = o;
     return b;
@@ -479,16 +480,21 @@ __device__ __forceinline__ void form_factor(BLU<CW> &F, const BL &L, const doubl
                     u1 = true;
                     F.pos1 = k;
 #pragma unroll
-                    for (int j = 0; j < CW; ++j) pb[part * CW + j] = e1[(size_t)(part * CW + j) * N];
+                    for (int j = 0; j < CW; ++j) pb[part * CWP + j] = e1[(size_t)(part * CW + j) * N];
                     if (part == pk) F.d1 = 1.0 / (double)cb[row];
                 }
                 if (active && row == p2) {
                     u2 = true;
                     F.pos2 = k;
+                    float4 *wr = reinterpret_cast<float4 *>(pb + NPB + part * CWP);
+                    float4 *wi = reinterpret_cast<float4 *>(pb + 2 * NPB + part * CWP);
 #pragma unroll
-                    for (int j = 0; j < CW; ++j) {
-                        pb[NPB + part * CW + j] = F.re[j];
-                        pb[2 * NPB + part * CW + j] = F.im[j];
+                    for (int j4 = 0; j4 < (CW + 3) / 4; ++j4) {
+                        const int j = 4 * j4;
+                        wr[j4] = make_float4(F.re[j], j + 1 < CW ? F.re[j + 1] : 0.0f, j + 2 < CW ? F.re[j + 2] : 0.0f,
+                                             j + 3 < CW ? F.re[j + 3] : 0.0f);
+                        wi[j4] = make_float4(F.im[j], j + 1 < CW ? F.im[j + 1] : 0.0f, j + 2 < CW ? F.im[j + 2] : 0.0f,
+                                             j + 3 < CW ? F.im[j + 3] : 0.0f);
                     }
                     if (part == pk) {
                         const double mr = F.re[c], mi = F.im[c];
@@ -517,13 +523,24 @@ __device__ __forceinline__ void form_factor(BLU<CW> &F, const BL &L, const doubl
                 // registers, then E1 in LDS in batches of 8 columns whose loads
                 // all issue before the batch's stores
                 if (!u2 && part >= pk) {
+                    // the pivot row four entries per LDS read
+                    const float4 *pr4 = reinterpret_cast<const float4 *>(pb + NPB + part * CWP);
+                    const float4 *pi4 = reinterpret_cast<const float4 *>(pb + 2 * NPB + part * CWP);
 #pragma unroll
-                    for (int j = 0; j < CW; ++j)
-                        if (j > c || part > pk) {
-                            const float ur = pb[NPB + part * CW + j], ui = pb[2 * NPB + part * CW + j];
-                            F.re[j] = fmaf(-lr, ur, fmaf(li, ui, F.re[j]));
-                            F.im[j] = fmaf(-lr, ui, fmaf(-li, ur, F.im[j]));
+                    for (int j4 = 0; j4 < (CW + 3) / 4; ++j4) {
+                        if (4 * j4 + 3 > c || part > pk) {
+                            const float4 a4 = pr4[j4], b4 = pi4[j4];
+                            const float urv[4] = {a4.x, a4.y, a4.z, a4.w}, uiv[4] = {b4.x, b4.y, b4.z, b4.w};
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) {
+                                const int j = 4 * j4 + u;
+                                if (j < CW && (j > c || part > pk)) {
+                                    F.re[j] = fmaf(-lr, urv[u], fmaf(li, uiv[u], F.re[j]));
+                                    F.im[j] = fmaf(-lr, uiv[u], fmaf(-li, urv[u], F.im[j]));
+                                }
+                            }
                         }
+                    }
                 }
                 if (!u1 && part >= pk) {
                     constexpr int UB = 8;
@@ -535,7 +552,7 @@ __device__ __forceinline__ void form_factor(BLU<CW> &F, const BL &L, const doubl
                             const int j = j0 + u;
                             const bool on = j < CW && (j > c || part > pk);
                             ev[u] = on ? e1[(size_t)(part * CW + j) * N] : 0.0f;
-                            pv[u] = on ? pb[part * CW + j] : 0.0f;
+                            pv[u] = on ? pb[part * CWP + j] : 0.0f;
                         }
 #pragma unroll
                         for (int u = 0; u < UB; ++u) {
