@@ -263,7 +263,10 @@ __device__ __forceinline__ double rhs_b(const DevMech &m, const BL &L, int t, do
 // accumulates column t (species t - 1) over the reactions with non-returning
 // atomic adds (the lane's own column, so the adds land in program order and
 // the result is deterministic; no round trip per update), then owns row t
-// for the final species-row pass.
+// for the final species-row pass.  A third-body term nu_kj ctb_j eff_j(m) is
+// split as nu_kj ctb_j (1 + (eff_j(m) - 1)): the first part is the same for
+// every column m of row k, so it is summed per row (c_k) and added in the
+// species-row pass; only efficiencies other than 1 go through the columns.
 __device__ __forceinline__ void jac_b(const DevMech &m, const BL &L, int t, double yv, double P, double *JS, int LDJ,
                                       int &ph) {
     const int K = m.K, R = m.R, N = m.N;
@@ -273,7 +276,7 @@ __device__ __forceinline__ void jac_b(const DevMech &m, const BL &L, int t, doub
     for (int i = t; i < N * LDJ; i += BT) JS[i] = 0.0;
     __syncthreads();
     double *col = JS + (size_t)(t < N ? t : 0) * LDJ;
-    double wdot = 0.0, dwdT = 0.0, sS = 0.0;
+    double wdot = 0.0, dwdT = 0.0, sS = 0.0, ck = 0.0;
     int i = x.isY ? m.sp_off[x.k] : 0;
     const int iend = x.isY ? m.sp_off[x.k + 1] : 0;
     double *rec = L.q;
@@ -317,7 +320,7 @@ __device__ __forceinline__ void jac_b(const DevMech &m, const BL &L, int t, doub
                 if (mm == sp.y) dq += rc[5];
                 if (mm == sp.z) dq += rc[6];
                 if (mm == sp.w) dq += rc[7];
-                if (info & 15) dq += rc[3] * m.eff[(size_t)((info >> 12) - 1) * K + mm];
+                if (info & 15) dq += rc[3] * (m.eff[(size_t)((info >> 12) - 1) * K + mm] - 1.0);
                 if (dq != 0.0) {
                     unsafeAtomicAdd(col + 1 + sp.x, -dq);
                     if (sp.y >= 0) unsafeAtomicAdd(col + 1 + sp.y, -dq);
@@ -333,6 +336,7 @@ __device__ __forceinline__ void jac_b(const DevMech &m, const BL &L, int t, doub
             wdot += e.y * rc[0];
             dwdT += e.y * rc[1];
             sS += e.y * rc[2];
+            ck += e.y * rc[3];      // third-body coefficient (0 for elementary reactions)
         }
         __syncthreads();
     }
@@ -342,13 +346,14 @@ __device__ __forceinline__ void jac_b(const DevMech &m, const BL &L, int t, doub
     bsum2(cpmix, dcpmix, L.red, ph);
     double hw = x.isY ? hk * wdot : 0.0, dHdT = x.isY ? th.cp * wdot + hk * (dwdT - sS * invT) : 0.0;
     bsum2(hw, dHdT, L.red, ph);
-    double hsS = x.isY ? hk * sS : 0.0, unused = 0.0;
-    bsum2(hsS, unused, L.red, ph);
+    double hsS = x.isY ? hk * sS : 0.0, hck = x.isY ? hk * ck : 0.0;
+    bsum2(hsS, hck, L.red, ph);
     const double rcp = rho * cpmix;
     const double fT = -hw / rcp;
     if (x.isY) {
         double hM = 0.0;
         for (int k = 0; k < K; ++k) hM += L.h[k] * T * col[1 + k];
+        hM += hck;      // the rows' third-body constants, summed with the enthalpies
         const double dHdY = (rho * hM - Wbar * hsS) * x.invW;
         col[0] = -dHdY / rcp - fT * (th.cp * x.invW / cpmix - Wbar * x.invW);
     }
@@ -368,7 +373,7 @@ __device__ __forceinline__ void jac_b(const DevMech &m, const BL &L, int t, doub
             for (int u = 0; u < 16; ++u) v[u] = c0 + u <= K ? JS[(size_t)(c0 + u) * LDJ + t] : 0.0;
 #pragma unroll
             for (int u = 0; u < 16; ++u)
-                if (c0 + u <= K) JS[(size_t)(c0 + u) * LDJ + t] = (Wk * v[u] + a) * iw[c0 + u - 1];
+                if (c0 + u <= K) JS[(size_t)(c0 + u) * LDJ + t] = (Wk * (v[u] + ck) + a) * iw[c0 + u - 1];
         }
     }
     __syncthreads();
