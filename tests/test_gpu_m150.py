@@ -156,3 +156,17 @@ def test_m150_group_variants_refused(torch_dev, g150):
         with pytest.raises(RkError):
             g150.integrate(_dev(torch_dev, rows), 1e-6)
     g150.set_option("variant", "auto")
+
+
+def test_block_variant_refused_small(torch_dev):
+    """The block variant refuses mechanisms with N <= 56 (the wavefront
+    kernels own that range) with an error instead of running."""
+    banner("block variant refused for M13")
+    from paper_1607_03884_amd import Mechanism
+    from paper_1607_03884_amd._lib import RkError
+    g = Mechanism(configs.mech_path("M13"))
+    g.set_option("variant", "block")
+    rows = configs.states_for(configs.WORKLOADS["cfg0"], 8)
+    with pytest.raises(RkError):
+        g.integrate(_dev(torch_dev, rows), 1e-6)
+    g.close()
