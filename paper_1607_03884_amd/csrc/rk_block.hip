@@ -162,13 +162,24 @@ __device__ __forceinline__ MixB mixture_b(const DevMech &m, const BL &L, int t, 
     __syncthreads();
     // [M] of every efficiency row, once per evaluation: wavefront w takes rows
     // w, w + 8, ...; its lanes read the row coalesced and reduce in a fixed order
+    // (four rows per pass, so the loads of the four overlap)
     const int w = wave_of(t), ln = t & 63, K = m.K;
-    for (int b = w; b < m.n3b; b += 8) {
-        const double *er = m.eff + (size_t)b * K;
-        double acc = 0.0;
-        for (int k = ln; k < K; k += 64) acc += er[k] * L.C[k];
-        acc = gsum<64>(acc);
-        if (ln == 0) L.Mc[b] = acc;
+    for (int b0 = w; b0 < m.n3b; b0 += 32) {
+        double acc[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int b = b0 + 8 * u;
+            acc[u] = 0.0;
+            if (b < m.n3b) {
+                const double *er = m.eff + (size_t)b * K;
+                for (int k = ln; k < K; k += 64) acc[u] += er[k] * L.C[k];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const double v = gsum<64>(acc[u]);
+            if (ln == 0 && b0 + 8 * u < m.n3b) L.Mc[b0 + 8 * u] = v;
+        }
     }
     __syncthreads();
     return x;
