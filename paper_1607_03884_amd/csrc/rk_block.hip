@@ -496,7 +496,13 @@ __device__ __forceinline__ void form_factor(BLU<CW> &F, const BL &L, const doubl
                     u1 = true;
                     F.pos1 = k;
 #pragma unroll
-                    for (int j = 0; j < CW; ++j) pb[part * CWP + j] = e1[(size_t)(part * CW + j) * N];
+                    for (int j4 = 0; j4 < (CW + 3) / 4; ++j4) {
+                        const int j = 4 * j4;
+                        const float *ec = e1 + (size_t)(part * CW + j) * N;
+                        reinterpret_cast<float4 *>(pb + part * CWP)[j4] =
+                            make_float4(ec[0], j + 1 < CW ? ec[N] : 0.0f, j + 2 < CW ? ec[2 * (size_t)N] : 0.0f,
+                                        j + 3 < CW ? ec[3 * (size_t)N] : 0.0f);
+                    }
                     if (part == pk) F.d1 = 1.0 / (double)cb[row];
                 }
                 if (active && row == p2) {
