@@ -67,9 +67,17 @@ typedef struct rk_stats {
     int32_t grid_used;        /* blocks launched for the integrator */
     int64_t predictor_kept;     /* states whose predicted first step converged */
     int64_t predictor_fallback; /* states restarted cold after the prediction failed */
+    /* D (Eq. 3) over groups of 64 consecutive entries of the work-queue order
+     * the integrator drew states in (equal to d_hist64 when no bins are used) */
+    int64_t d_hist64_queue[20];
+    double d_mean64_queue;
 } rk_stats;
 
 /* mech_load — read a mechanism file and upload it to the current device.
+ * Defines the source terms the integrator works on: the paper integrates
+ * constant-pressure, mass-fraction-based reactor equations whose rates and
+ * analytical Jacobian come from a chemical kinetic model of species
+ * thermodynamics and reversible reactions (Sec. 2.1; test models Sec. 2.2).
  *   path: text mechanism (species with element counts and molar masses,
  *         two-range NASA-7 thermodynamics, reversible reactions with 1-2
  *         species per side: elementary, third-body, Troe falloff; SI units).
@@ -86,7 +94,12 @@ void mech_free(rk_mech *mech);
 /* mech_dims — number of species K and reactions R of a handle. */
 int mech_dims(const rk_mech *mech, int32_t *K, int32_t *R);
 
-/* radau_integrate — integrate n_states independent states over [0, dt].
+/* radau_integrate — integrate n_states independent states over [0, dt]:
+ * the paper's batched problem (Sec. 2.1, Sec. 2.2): every state is an
+ * independent constant-pressure adiabatic reactor advanced over one global
+ * time step by the three-stage fifth-order Radau IIA method with adaptive
+ * steps under the absolute and relative tolerances of Sec. 2.1 (paper:
+ * atol 1e-10, rtol 1e-6); global steps of 1e-6 s and 1e-4 s in Sec. 3.
  *   d_y_in, d_y_out: device arrays of (K+2)*n_states doubles, component-major
  *       (struct of arrays): element (c, i) at c*n_states + i, c = 0 temperature
  *       [K], c = 1..K mass fractions Y_k, c = K+1 pressure [Pa].  Pressure is
@@ -103,7 +116,10 @@ int mech_dims(const rk_mech *mech, int32_t *K, int32_t *R);
 int radau_integrate(rk_mech *mech, int64_t n_states, double dt, const double *d_y_in, double *d_y_out,
                     double atol, double rtol, void *stream);
 
-/* stats_get — statistics of the last radau_integrate on this handle.
+/* stats_get — statistics of the last radau_integrate on this handle,
+ * including the thread-divergence measure D of Eq. (3) (Sec. 3.3) over
+ * groups of 64 and 32 consecutive states of the input order and over the
+ * groups of 64 consecutive states of the executed work-queue order.
  * Synchronises that call's stream.  per_state_steps and per_state_status are
  * optional HOST arrays of n_states int32 (step attempts, status code). */
 int stats_get(rk_mech *mech, rk_stats *out, int32_t *per_state_steps, int32_t *per_state_status);
@@ -157,7 +173,17 @@ int stats_get(rk_mech *mech, rk_stats *out, int32_t *per_state_steps, int32_t *p
  *              K is refused (RK_EINVAL).  "none" removes all predictors.
  *   "predictor_use" "both" (default) | "h0" (predicted first step size only,
  *              stage values start at zero) | "z0" (predicted stage values with
- *              the default first step size): ablations of the predictor
+ *              the default first step size) | "bins" (no warm start: the
+ *              network only keys the cost bins by its predicted step counts,
+ *              so every state's result is bitwise that of a cold start)
+ *   "force_fallback" "0" (default) | "1": test switch of the FP32 variants'
+ *              fallbacks: "mixed" hands every state to the FP64 pass at its
+ *              first accepted step; "block" switches every state to
+ *              FP64-accurate solves after its first accepted step
+ *   "block_solves" "fp32_refined" (default) | "fp64_accurate": the block
+ *              variant refines every solve three times from the first step
+ *              (FP64-accurate solves from FP32 factors and FP64 residuals;
+ *              counted in fp32_fallback)
  *   "kmax"     max Newton iterations per step (default 7)
  *   "kappa"    Newton stopping constant (default max(10u/rtol, min(0.03, rtol^0.5)))
  *   "nmax"     step-attempt limit per state (default 100000)
@@ -177,6 +203,24 @@ int rk_dbg_rhs(rk_mech *mech, int64_t n, const double *d_y, double *d_f, void *s
 /* rk_dbg_jacobian — analytical Jacobian for n states: d_J receives
  * (K+1)^2 * n doubles, element (r, c) of state i at (r*(K+1) + c)*n + i. */
 int rk_dbg_jacobian(rk_mech *mech, int64_t n, const double *d_y, double *d_J, void *stream);
+
+/* rk_dbg_lu_solve — the integrator's own formation, LU factorisation with
+ * partial pivoting and substitutions of the two Radau IIA iteration matrices
+ * (the real and complex systems of the transformed simplified Newton
+ * iteration that the paper's Radau IIA solves, Sec. 2.1), applied to given
+ * Jacobians: x1 = E1^-1 b1 and x2 + i x3 = E2^-1 (b2 + i b3), with
+ * E1 = g/h I - J and E2 = (a + i b)/h I - J (g, a +- i b the eigenvalues of
+ * the inverse Radau IIA coefficient matrix).  K + 1 <= 56 (wavefront kernels).
+ *   fp32: 0 = FP64 factors; 1 = FP32 factors of the matrices equilibrated with
+ *         the error weights d_sc, solved without refinement (the factors' own
+ *         accuracy).
+ *   d_J: (K+1)^2 * n doubles as rk_dbg_jacobian; d_sc: (K+1) * n error
+ *   weights (component-major, used by fp32 = 1); d_b, d_x: 3 (K+1) n doubles,
+ *   element (v, r) of system i at (v (K+1) + r) n + i, v = 0 real right-hand
+ *   side / solution, v = 1, 2 real and imaginary parts of the complex one.
+ * RK_EINVAL for n < 0, h <= 0, K + 1 > 56 or non-device arrays. */
+int rk_dbg_lu_solve(rk_mech *mech, int64_t n, int fp32, double h, const double *d_J, const double *d_sc,
+                    const double *d_b, double *d_x, void *stream);
 
 /* ---- learned stage/step predictor network --------------------------------
  * A multilayer perceptron with widths dims[0] -> ... -> dims[n-1], GELU

@@ -27,11 +27,12 @@ class RkStats(ctypes.Structure):
                 ("d_hist64", ctypes.c_int64 * 20), ("d_hist32", ctypes.c_int64 * 20),
                 ("d_mean64", ctypes.c_double), ("d_mean32", ctypes.c_double), ("kernel_ms", ctypes.c_double),
                 ("fp32_fallback", ctypes.c_int64), ("nbins_used", ctypes.c_int32), ("grid_used", ctypes.c_int32),
-                ("predictor_kept", ctypes.c_int64), ("predictor_fallback", ctypes.c_int64)]
+                ("predictor_kept", ctypes.c_int64), ("predictor_fallback", ctypes.c_int64),
+                ("d_hist64_queue", ctypes.c_int64 * 20), ("d_mean64_queue", ctypes.c_double)]
 
 
 EXPORTS = ["mech_load", "mech_free", "mech_dims", "radau_integrate", "stats_get", "radau_set_option",
-           "rk_last_error", "rk_dbg_rhs", "rk_dbg_jacobian",
+           "rk_last_error", "rk_dbg_rhs", "rk_dbg_jacobian", "rk_dbg_lu_solve",
            "rk_mlp_create", "rk_mlp_free", "rk_mlp_param_count", "rk_mlp_set_params", "rk_mlp_get_params",
            "rk_mlp_forward", "rk_mlp_grads", "rk_mlp_train_step", "rk_mlp_last_error"]
 
@@ -59,6 +60,7 @@ def lib():
         L.rk_last_error.restype = ctypes.c_char_p
         L.rk_dbg_rhs.argtypes = [vp, i64, vp, vp, vp]
         L.rk_dbg_jacobian.argtypes = [vp, i64, vp, vp, vp]
+        L.rk_dbg_lu_solve.argtypes = [vp, i64, ctypes.c_int, dbl, vp, vp, vp, vp, vp]
         L.rk_mlp_create.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(vp)]
         L.rk_mlp_free.argtypes = [vp]
         L.rk_mlp_free.restype = None
@@ -144,6 +146,7 @@ class Mechanism:
         out = {f: getattr(s, f) for f, _ in RkStats._fields_ if not f.startswith("d_hist")}
         out["d_hist64"] = list(s.d_hist64)
         out["d_hist32"] = list(s.d_hist32)
+        out["d_hist64_queue"] = list(s.d_hist64_queue)
         if per_state:
             out["per_state_steps"] = steps
             out["per_state_status"] = status
@@ -168,3 +171,18 @@ class Mechanism:
         _check(lib().rk_dbg_jacobian(self._h, y.shape[1], y.data_ptr(), J.data_ptr(), _stream_ptr(stream)),
                "rk_dbg_jacobian")
         return J
+
+    def dbg_lu_solve(self, J, b, h: float, fp32: bool = False, sc=None, stream=None):
+        """x1 = E1^-1 b1, x2 + i x3 = E2^-1 (b2 + i b3) with the integrator's own
+        factorisation (J: [N*N, n], b: [3*N, n], sc: [N, n] error weights)."""
+        import torch
+        n = J.shape[1]
+        for t, rows, name in ((J, self.N * self.N, "J"), (b, 3 * self.N, "b")):
+            if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous() or tuple(t.shape) != (rows, n):
+                raise RkError(f"{name} must be a contiguous float64 CUDA tensor of shape [{rows}, {n}]")
+        if sc is None:
+            sc = torch.ones((self.N, n), dtype=torch.float64, device=J.device)
+        x = torch.empty_like(b)
+        _check(lib().rk_dbg_lu_solve(self._h, n, int(bool(fp32)), float(h), J.data_ptr(), sc.data_ptr(),
+                                     b.data_ptr(), x.data_ptr(), _stream_ptr(stream)), "rk_dbg_lu_solve")
+        return x

@@ -46,6 +46,8 @@ WORKLOADS = {
     "cfg0": Workload("cfg0", "M13", 4096, (DT_SMALL,), "uniform", 1000),
     "cfg1": Workload("cfg1", "M13", 262144, (DT_SMALL, DT_LARGE), "pasr", 1001),
     "cfg2": Workload("cfg2", "M53", 131072, (DT_SMALL, DT_LARGE), "pasr", 1002),
+    # the 53-species states of cfg2 with the learned predictor
+    "cfg3": Workload("cfg3", "M53", 131072, (DT_SMALL, DT_LARGE), "pasr", 1002),
     "cfg4": Workload("cfg4", "M150", 65536, (DT_LARGE,), "pasr", 1004),
 }
 

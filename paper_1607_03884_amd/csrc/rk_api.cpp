@@ -710,13 +710,25 @@ int radau_set_option(rk_mech *m, const char *key, const char *value) {
         if (v == "both") m->pred_use = 3;
         else if (v == "h0") m->pred_use = 1;
         else if (v == "z0") m->pred_use = 2;
-        else return fail(RK_EINVAL, "predictor_use: both | h0 | z0");
+        else if (v == "bins") m->pred_use = 0;
+        else return fail(RK_EINVAL, "predictor_use: both | h0 | z0 | bins");
         return RK_OK;
     }
     if (k == "autotune") {
         if (v != "0" && v != "1") return fail(RK_EINVAL, "autotune: 0 or 1");
         m->autotune = v == "1";
         if (!m->autotune) m->tuned.clear();
+        return RK_OK;
+    }
+    if (k == "force_fallback") {
+        if (v != "0" && v != "1") return fail(RK_EINVAL, "force_fallback: 0 or 1");
+        m->force_fb = v == "1";
+        return RK_OK;
+    }
+    if (k == "block_solves") {
+        if (v == "fp32_refined") m->fp64_solves = 0;
+        else if (v == "fp64_accurate") m->fp64_solves = 1;
+        else return fail(RK_EINVAL, "block_solves: fp32_refined | fp64_accurate");
         return RK_OK;
     }
     if (k == "kappa" || k == "h0") {
@@ -756,6 +768,8 @@ int radau_integrate(rk_mech *m, int64_t n, double dt, const double *yin, double 
     p.kmax = m->kmax;
     p.nmax = m->nmax;
     p.pred_use = m->pred_use;
+    p.force_fb = m->force_fb;
+    p.fp64_solves = m->fp64_solves;
     p.kappa = m->kappa > 0.0 ? m->kappa : std::max(10.0 * 2.220446049250313e-16 / rtol, std::min(0.03, std::sqrt(rtol)));
     p.h0 = m->h0 > 0.0 ? m->h0 : std::min(dt, 1e-6);
     int nbins = m->nbins, gpct = m->grid_pct;
@@ -789,7 +803,8 @@ int stats_get(rk_mech *m, rk_stats *out, int32_t *steps, int32_t *status) {
     std::vector<int32_t> c((size_t)n * rk::kNumCounters);
     e = hipMemcpy(c.data(), m->counters, c.size() * sizeof(int32_t), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpy of counters");
-    const int32_t *st = &c[(size_t)rk::C_STATUS * n], *ns = &c[(size_t)rk::C_NSTEP * n];
+    const int32_t *st = &c[(size_t)rk::C_STATUS * n];
+    const int32_t *ns = &c[(size_t)rk::C_NSTEP * n];
     out->max_steps = 0;
     out->min_steps = ns[0];
     for (int64_t i = 0; i < n; ++i) {
@@ -829,9 +844,24 @@ int stats_get(rk_mech *m, rk_stats *out, int32_t *steps, int32_t *status) {
     };
     hist(64, out->d_hist64, &out->d_mean64);
     hist(32, out->d_hist32, &out->d_mean32);
+    // the same measure over the work-queue order the integrator drew states in
+    // (how well the cost bins put states of equal step counts next to each other)
+    if (m->last_nbins > 0 && m->order) {
+        std::vector<int32_t> ord((size_t)n), qs((size_t)n);
+        e = hipMemcpy(ord.data(), m->order, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpy of the queue order");
+        for (int64_t q = 0; q < n; ++q) qs[q] = ns[ord[q]];
+        const int32_t *keep = ns;
+        ns = qs.data();
+        hist(64, out->d_hist64_queue, &out->d_mean64_queue);
+        ns = keep;
+    } else {
+        std::memcpy(out->d_hist64_queue, out->d_hist64, sizeof out->d_hist64);
+        out->d_mean64_queue = out->d_mean64;
+    }
     out->nbins_used = m->last_nbins;
     out->grid_used = m->last_grid;
-    if (steps) std::memcpy(steps, ns, (size_t)n * sizeof(int32_t));
+    if (steps) std::memcpy(steps, &c[(size_t)rk::C_NSTEP * n], (size_t)n * sizeof(int32_t));
     if (status) std::memcpy(status, st, (size_t)n * sizeof(int32_t));
     return RK_OK;
 }
@@ -857,6 +887,24 @@ int rk_dbg_jacobian(rk_mech *m, int64_t n, const double *y, double *J, void *str
     if (rc != RK_OK) return rc;
     hipError_t e = rk::launch_jac(m->dev, n, y, J, m->scratch, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? RK_OK : hip_fail(e, "jacobian kernel launch");
+}
+
+int rk_dbg_lu_solve(rk_mech *m, int64_t n, int fp32, double h, const double *J, const double *sc, const double *b,
+                    double *x, void *stream) {
+    if (!m) return fail(RK_EINVAL, "NULL handle");
+    if (n < 0 || !(h > 0.0) || !std::isfinite(h) || (fp32 != 0 && fp32 != 1))
+        return fail(RK_EINVAL, "rk_dbg_lu_solve: need n >= 0, h > 0, fp32 in {0, 1}");
+    if (!rk::group_supported(m->K + 1))
+        return fail(RK_EINVAL, "rk_dbg_lu_solve: the wavefront factorisation covers K + 1 <= 56");
+    if (n > 0) {
+        for (const void *q : {(const void *)J, (const void *)sc, (const void *)b, (const void *)x})
+            if (!q || !is_device_ptr(q)) return fail(RK_EINVAL, "rk_dbg_lu_solve: arrays must be device memory");
+    }
+    rk::RadauParams p{};
+    radau_constants(p);
+    hipError_t e = rk::launch_lu_solve(m->K + 1, fp32 == 1, n, p.g / h, p.a / h, p.b / h, J, sc, b, x,
+                                       static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? RK_OK : hip_fail(e, "lu_solve kernel launch");
 }
 
 }  // extern "C"

@@ -786,8 +786,8 @@ __global__ __launch_bounds__(BT) void radau_block_kernel(DevMech m, RadauParams 
             }
             have = true;
             status = RK_ST_OK;
-            flags = 0;
-            fb = false;
+            flags = rp.fp64_solves ? kFlagFp32Fallback : 0;
+            fb = rp.fp64_solves != 0;
             h = rp.h0;
             last = false;
             if (1.0001 * h >= dt) { h = dt; last = true; }
@@ -966,6 +966,10 @@ __global__ __launch_bounds__(BT) void radau_block_kernel(DevMech m, RadauParams 
                     first = false;
                     ndiv_row = 0;
                     ++nacc;
+                    if (rp.force_fb && !fb) {    // host-forced switch (tests of the FP64-accurate solves)
+                        fb = true;
+                        flags |= kFlagFp32Fallback;
+                    }
                     const double hacc = L.hist[0], eacc = L.hist[1];
                     if (nacc > 1) {
                         double fg = (hacc / h) * pow(err * err / eacc, 0.25) / 0.9;

@@ -89,6 +89,15 @@ hipError_t launch_radau_group(const DevMech &m, const RadauParams &p, int64_t n,
     return launch_shape(g, false, m, p, n, yin, yout, counters, queue + 2, fb_list, queue + 1, nullptr, grid, st);
 }
 
+hipError_t launch_lu_solve(int N, bool fp32, int64_t n, double gh, double ah, double bh, const double *J,
+                           const double *sc, const double *b, double *x, hipStream_t st) {
+    const GroupShape g = group_shape(N);
+    if (!g.G) return hipErrorInvalidValue;
+    if (n == 0) return hipSuccess;
+    if (g.G == 16) return lu_solve_group16(g.NC, fp32, N, n, gh, ah, bh, J, sc, b, x, st);
+    return lu_solve_group64(g.NC, fp32, N, n, gh, ah, bh, J, sc, b, x, st);
+}
+
 int group_max_blocks(const DevMech &m) {
     const GroupShape g = group_shape(m.N);
     if (!g.G) return 1;

@@ -22,6 +22,21 @@ hipError_t launch_group16(int NC, bool fp32, const DevMech &m, const RadauParams
     return hipErrorInvalidValue;
 }
 
+hipError_t lu_solve_group16(int NC, bool fp32, int N, int64_t n, double gh, double ah, double bh, const double *J,
+                            const double *sc, const double *b, double *x, hipStream_t st) {
+    if (NC == 14) {
+        if (fp32) launch_lu_solve_one<float, 16, 14>(N, n, gh, ah, bh, J, sc, b, x, st);
+        else launch_lu_solve_one<double, 16, 14>(N, n, gh, ah, bh, J, sc, b, x, st);
+        return hipGetLastError();
+    }
+    if (NC == 16) {
+        if (fp32) launch_lu_solve_one<float, 16, 16>(N, n, gh, ah, bh, J, sc, b, x, st);
+        else launch_lu_solve_one<double, 16, 16>(N, n, gh, ah, bh, J, sc, b, x, st);
+        return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
+}
+
 int occupancy_group16(int NC, size_t lds) {
     if (NC == 14) return std::min(occupancy_one<double, 16, 14>(lds), occupancy_one<float, 16, 14>(lds));
     if (NC == 16) return std::min(occupancy_one<double, 16, 16>(lds), occupancy_one<float, 16, 16>(lds));

@@ -22,6 +22,21 @@ hipError_t launch_group64(int NC, bool fp32, const DevMech &m, const RadauParams
     return hipErrorInvalidValue;
 }
 
+hipError_t lu_solve_group64(int NC, bool fp32, int N, int64_t n, double gh, double ah, double bh, const double *J,
+                            const double *sc, const double *b, double *x, hipStream_t st) {
+    if (NC == 54) {
+        if (fp32) launch_lu_solve_one<float, 64, 54>(N, n, gh, ah, bh, J, sc, b, x, st);
+        else launch_lu_solve_one<double, 64, 54>(N, n, gh, ah, bh, J, sc, b, x, st);
+        return hipGetLastError();
+    }
+    if (NC == 56) {
+        if (fp32) launch_lu_solve_one<float, 64, 56>(N, n, gh, ah, bh, J, sc, b, x, st);
+        else launch_lu_solve_one<double, 64, 56>(N, n, gh, ah, bh, J, sc, b, x, st);
+        return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
+}
+
 int occupancy_group64(int NC, size_t lds) {
     if (NC == 54) return std::min(occupancy_one<double, 64, 54>(lds), occupancy_one<float, 64, 54>(lds));
     if (NC == 56) return std::min(occupancy_one<double, 64, 56>(lds), occupancy_one<float, 64, 56>(lds));

@@ -605,6 +605,54 @@ __device__ __forceinline__ void factor_cplx(LUC<S, NC> &F, const GL &L, int r, i
     F.src = src;
 }
 
+// The two iteration matrices of a step from the lane's row of J (unit stride,
+// NC entries): E1 = gh I - J (real), E2 = (ah + i bh) I - J (complex).  With
+// FP32 factors they are equilibrated first: E'' = diag(1/(sc_r m_r)) E diag(sc_c),
+// the column scaling applied in FP64 before rounding, the row factor m_r (the
+// power of two at or below the row maximum, so exact) afterwards.
+template <typename S, int G, int NC>
+__device__ __forceinline__ void form_matrices(LUR<S, NC> &E1, LUC<S, NC> &E2, const double *row, bool comp, int r,
+                                              double scv, double gh, double ah, double bh) {
+    if constexpr (std::is_same<S, float>::value) {
+        double m1 = 0.0, m2 = 0.0;
+        const double isc = 1.0 / scv;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const double j = comp ? row[c] : 0.0;
+            const double w = bcast<G>(scv, c) * isc;
+            const double v1 = ((c == r ? gh : 0.0) - j) * w, v2 = ((c == r ? ah : 0.0) - j) * w;
+            m1 = fmax(m1, fabs(v1));
+            m2 = fmax(m2, fabs(v2));
+            E1.a[c] = (S)v1;
+            E2.re[c] = (S)v2;
+        }
+        const double e2i = bh;      // imaginary part: diagonal only, scale w = 1
+        m2 = fmax(m2, e2i);
+        const double i1 = 1.0 / exp2(floor(log2(m1))), i2 = 1.0 / exp2(floor(log2(m2)));
+        const S f1 = (S)i1, f2 = (S)i2;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            E1.a[c] *= f1;
+            E2.re[c] *= f2;
+            E2.im[c] = (S)(c == r ? e2i * i2 : 0.0);
+        }
+        E1.rs = isc * i1;
+        E2.rs = isc * i2;
+        E1.cs = E2.cs = scv;
+    } else {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const double j = comp ? row[c] : 0.0;
+            E1.a[c] = -j;
+            E2.re[c] = -j;
+            E2.im[c] = 0.0;
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            if (c == r) { E1.a[c] += gh; E2.re[c] += ah; E2.im[c] = bh; }
+    }
+}
+
 // factor entry widened to double at its point of use: the empty asm keeps the
 // compiler from hoisting the conversions of all entries out of the Newton loop
 // (which would hold a double copy of both factorisations in registers)
@@ -823,52 +871,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(G == 16 ? 2 
             action = ACT_LU;
         }
         if (action == ACT_LU) {
-            const double gh = rp.g / h, ah = rp.a / h, bh = rp.b / h;
-            const double *row = L.J + (r < NC ? r : 0) * (NC + 1);
-            if constexpr (kMixed) {
-                // equilibrate: E'' = diag(1/(sc_r m_r)) E diag(sc_c).  The column
-                // scaling is applied in FP64 before rounding, the row factor m_r (the
-                // power of two at or below the row maximum, so exact) afterwards
-                const double scv = scw();
-                double m1 = 0.0, m2 = 0.0;
-                const double isc = 1.0 / scv;
-#pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    const double j = comp ? row[c] : 0.0;
-                    const double w = bcast<G>(scv, c) * isc;
-                    const double v1 = ((c == r ? gh : 0.0) - j) * w, v2 = ((c == r ? ah : 0.0) - j) * w;
-                    m1 = fmax(m1, fabs(v1));
-                    m2 = fmax(m2, fabs(v2));
-                    E1.a[c] = (S)v1;
-                    E2.re[c] = (S)v2;
-                }
-                const double e2i = bh;      // imaginary part: diagonal only, scale w = 1
-                m2 = fmax(m2, e2i);
-                const double i1 = 1.0 / exp2(floor(log2(m1))), i2 = 1.0 / exp2(floor(log2(m2)));
-                const S f1 = (S)i1, f2 = (S)i2;
-#pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    E1.a[c] *= f1;
-                    E2.re[c] *= f2;
-                    E2.im[c] = (S)(c == r ? e2i * i2 : 0.0);
-                }
-                E1.rs = isc * i1;
-                E2.rs = isc * i2;
-                E1.cs = E2.cs = scv;
-                sync_wave();
-            } else {
-#pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    const double j = comp ? row[c] : 0.0;
-                    E1.a[c] = -j;
-                    E2.re[c] = -j;
-                    E2.im[c] = 0.0;
-                }
-#pragma unroll
-                for (int c = 0; c < NC; ++c)
-                    if (c == r) { E1.a[c] += gh; E2.re[c] += ah; E2.im[c] = bh; }
-                sync_wave();
-            }
+            form_matrices<S, G, NC>(E1, E2, L.J + (r < NC ? r : 0) * (NC + 1), comp, r, scw(), rp.g / h, rp.a / h,
+                                    rp.b / h);
+            sync_wave();
             factor_real<S, G>(E1, L, r, N);
             factor_cplx<S, G>(E2, L, r, N);
             bump(K_NLU, 1);
@@ -1037,7 +1042,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(G == 16 ? 2 
                     const double t = last ? dt : L.hist[4] + h;
                     L.hist[4] = t;
                     jac_fresh = false;
-                    if (last) {
+                    if (kMixed && rp.force_fb) {    // host-forced hand-back (tests of the FP64 pass)
+                        status = kStatusFallback;
+                        done = true;
+                    } else if (last) {
                         done = true;
                     } else {
                         const double f0 = rhs_g<G>(m, L, r, y, L.hist[3]);
@@ -1069,9 +1077,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(G == 16 ? 2 
             }
         }
         if (done) {
-            if (comp) yout[(size_t)r * n + s] = y;
+            // a state handed to the FP64 pass leaves y_out alone: that pass
+            // restarts it from y_in, which may be the same array
+            const bool handed = status == kStatusFallback;
+            if (comp && !handed) yout[(size_t)r * n + s] = y;
             if (r == 0) {
-                yout[(size_t)(K + 1) * n + s] = L.hist[3];
+                if (!handed) yout[(size_t)(K + 1) * n + s] = L.hist[3];
                 cnt[(size_t)C_STATUS * n + s] = status;
                 cnt[(size_t)C_NSTEP * n + s] = nstep;
                 cnt[(size_t)C_NACC * n + s] = nacc;
@@ -1090,6 +1101,59 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(G == 16 ? 2 
     }
 }
 
+
+
+// Kernel-level test entry: the integrator's own formation, factorisation and
+// substitutions applied to a given J.  One group per system; the system's J
+// (element (r, c) of system i at (r * N + c) * n + i) is staged in LDS in the
+// integrator's row layout.  x1 = E1^-1 b1 and x2 + i x3 = E2^-1 (b2 + i b3)
+// with E1 = g/h I - J, E2 = (a + i b)/h I - J; b and x are [3][N][n].  FP32
+// factors are equilibrated with the error weights sc ([N][n]) and solved
+// without refinement, so x shows the factors' own accuracy.
+template <typename S, int G, int NC>
+__global__ __launch_bounds__(64) void lu_solve_kernel(int N, int64_t n, double gh, double ah, double bh,
+                                                      const double *__restrict__ J, const double *__restrict__ sc,
+                                                      const double *__restrict__ b, double *__restrict__ x) {
+    extern __shared__ double smem[];
+    const int r = threadIdx.x & (G - 1), grp = threadIdx.x / G;
+    double *Js = smem + (size_t)grp * (NC * (NC + 1) + 2 * NC);
+    GL L{};
+    L.prow = Js + NC * (NC + 1);
+    const int64_t i = (int64_t)blockIdx.x * (kWave / G) + grp;
+    const bool live = i < n;
+    const bool comp = live && r < N;
+    for (int e = r; e < NC * (NC + 1); e += G) {
+        const int rr = e / (NC + 1), cc = e - rr * (NC + 1);
+        Js[e] = (live && rr < N && cc < N) ? J[((size_t)rr * N + cc) * n + i] : 0.0;
+    }
+    sync_wave();
+    LUR<S, NC> E1;
+    LUC<S, NC> E2;
+    const double scv = comp ? sc[(size_t)r * n + i] : 1.0;
+    form_matrices<S, G, NC>(E1, E2, Js + (r < NC ? r : 0) * (NC + 1), comp, r, scv, gh, ah, bh);
+    sync_wave();
+    factor_real<S, G>(E1, L, r, N);
+    factor_cplx<S, G>(E2, L, r, N);
+    double b1 = comp ? b[(size_t)r * n + i] : 0.0;
+    double b2 = comp ? b[((size_t)N + r) * n + i] : 0.0;
+    double b3 = comp ? b[((size_t)2 * N + r) * n + i] : 0.0;
+    b1 = solve_real<S, G>(E1, r, N, b1);
+    solve_cplx<S, G>(E2, r, N, b2, b3);
+    if (comp) {
+        x[(size_t)r * n + i] = b1;
+        x[((size_t)N + r) * n + i] = b2;
+        x[((size_t)2 * N + r) * n + i] = b3;
+    }
+}
+
+template <typename S, int G, int NC>
+void launch_lu_solve_one(int N, int64_t n, double gh, double ah, double bh, const double *J, const double *sc,
+                         const double *b, double *x, hipStream_t st) {
+    const int per = kWave / G;
+    const size_t lds = (size_t)per * (NC * (NC + 1) + 2 * NC) * sizeof(double);
+    hipLaunchKernelGGL((lu_solve_kernel<S, G, NC>), dim3((unsigned)((n + per - 1) / per)), dim3(kWave), lds, st, N,
+                       n, gh, ah, bh, J, sc, b, x);
+}
 
 // enqueue one instantiation on its persistent grid
 template <typename S, int G, int NC>

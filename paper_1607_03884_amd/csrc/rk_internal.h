@@ -40,6 +40,8 @@ struct RadauParams {
     double dt, atol, rtol, kappa, h0;
     int kmax, nmax;
     int pred_use;            // bit 1: predicted first step size, bit 2: predicted stage values
+    int force_fb;            // FP32 variants: take the fallback at the first accepted step (tests)
+    int fp64_solves;         // block variant: FP64-accurate solves (three refinement sweeps) from the start
     double g, a, b;          // eigenvalues of A^-1: g, a +- i b
     double T[9], Ti[9];      // T^-1 A^-1 T = [[g,0,0],[0,a,-b],[0,b,a]] (row-major)
     double c1, c2;           // collocation nodes (c3 = 1)
@@ -91,6 +93,14 @@ hipError_t launch_group16(int NC, bool fp32, const DevMech &m, const RadauParams
 hipError_t launch_group64(int NC, bool fp32, const DevMech &m, const RadauParams &p, int64_t n, const double *yin,
                           double *yout, int32_t *cnt, int *queue, const int *order, const int *work_n,
                           const double *pred, int grid, hipStream_t st);
+hipError_t lu_solve_group16(int NC, bool fp32, int N, int64_t n, double gh, double ah, double bh, const double *J,
+                            const double *sc, const double *b, double *x, hipStream_t st);
+hipError_t lu_solve_group64(int NC, bool fp32, int N, int64_t n, double gh, double ah, double bh, const double *J,
+                            const double *sc, const double *b, double *x, hipStream_t st);
+// factor and solve E1 = gh I - J, E2 = (ah + i bh) I - J with the group
+// kernels' routines (kernel-level test entry; N <= 56)
+hipError_t launch_lu_solve(int N, bool fp32, int64_t n, double gh, double ah, double bh, const double *J,
+                           const double *sc, const double *b, double *x, hipStream_t st);
 int occupancy_group16(int NC, size_t lds);
 int occupancy_group64(int NC, size_t lds);
 hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t st);
@@ -161,6 +171,7 @@ struct rk_mech {
     // options
     int variant = -1;          // -1 auto, 0 lane, 1 wave, 2 mixed (FP32 factors), 3 block (N > 56)
     int kmax = 7, nmax = 100000;
+    int force_fb = 0, fp64_solves = 0;
     double kappa = 0.0, h0 = 0.0;
     // workspace of the last call
     double *scratch = nullptr;
