@@ -116,6 +116,25 @@ int mech_dims(const rk_mech *mech, int32_t *K, int32_t *R);
 int radau_integrate(rk_mech *mech, int64_t n_states, double dt, const double *d_y_in, double *d_y_out,
                     double atol, double rtol, void *stream);
 
+/* radau_integrate_noalloc — radau_integrate for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same kernels and results as
+ * radau_integrate with the handle's "wave" or "mixed" variant in input order
+ * ("auto" runs "wave"), but every scratch buffer of the call (queue heads,
+ * FP32-to-FP64 hand-back list, per-state counters) lives in one static device
+ * array of 11.5 MB that each device holds for the life of the process;
+ * nothing is allocated, by the library or anything it calls.  The caller
+ * still passes the state arrays (as radau_integrate).  The predictor, cost
+ * bins and autotuner of the handle are not used.
+ * Limits: n_states <= 262144 (RK_EINVAL beyond); K + 1 <= 56 and variant
+ * "auto", "wave" or "mixed" (RK_EINVAL otherwise).
+ * Sharing: every call on a device uses that device's one array, so calls
+ * that overlap on a device (any handles, any streams) race and must be
+ * ordered by the caller; stats_get after this call reads the array, which
+ * the next no-allocation call on the device overwrites. */
+int radau_integrate_noalloc(rk_mech *mech, int64_t n_states, double dt, const double *d_y_in, double *d_y_out,
+                            double atol, double rtol, void *stream);
+
 /* stats_get — statistics of the last radau_integrate on this handle,
  * including the thread-divergence measure D of Eq. (3) (Sec. 3.3) over
  * groups of 64 and 32 consecutive states of the input order and over the

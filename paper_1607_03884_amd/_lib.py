@@ -31,7 +31,8 @@ class RkStats(ctypes.Structure):
                 ("d_hist64_queue", ctypes.c_int64 * 20), ("d_mean64_queue", ctypes.c_double)]
 
 
-EXPORTS = ["mech_load", "mech_free", "mech_dims", "radau_integrate", "stats_get", "radau_set_option",
+EXPORTS = ["mech_load", "mech_free", "mech_dims", "radau_integrate", "radau_integrate_noalloc", "stats_get",
+           "radau_set_option",
            "rk_last_error", "rk_dbg_rhs", "rk_dbg_jacobian", "rk_dbg_lu_solve",
            "rk_mlp_create", "rk_mlp_free", "rk_mlp_param_count", "rk_mlp_set_params", "rk_mlp_get_params",
            "rk_mlp_forward", "rk_mlp_grads", "rk_mlp_train_step", "rk_mlp_last_error"]
@@ -55,6 +56,7 @@ def lib():
         L.mech_free.restype = None
         L.mech_dims.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
         L.radau_integrate.argtypes = [vp, i64, dbl, vp, vp, dbl, dbl, vp]
+        L.radau_integrate_noalloc.argtypes = [vp, i64, dbl, vp, vp, dbl, dbl, vp]
         L.stats_get.argtypes = [vp, ctypes.POINTER(RkStats), vp, vp]
         L.radau_set_option.argtypes = [vp, ctypes.c_char_p, ctypes.c_char_p]
         L.rk_last_error.restype = ctypes.c_char_p
@@ -131,6 +133,19 @@ class Mechanism:
         _check_states(y_out, self.K + 2, "y_out")
         _check(lib().radau_integrate(self._h, n, float(dt), y_in.data_ptr(), y_out.data_ptr(), float(atol),
                                      float(rtol), _stream_ptr(stream)), "radau_integrate")
+        return y_out
+
+    def integrate_noalloc(self, y_in, dt: float, atol: float = 1e-10, rtol: float = 1e-6, y_out=None, stream=None):
+        """As integrate, through radau_integrate_noalloc (the library allocates
+        nothing; y_out must be given by callers that cannot allocate)."""
+        import torch
+        _check_states(y_in, self.K + 2, "y_in")
+        n = y_in.shape[1]
+        if y_out is None:
+            y_out = torch.empty_like(y_in)
+        _check_states(y_out, self.K + 2, "y_out")
+        _check(lib().radau_integrate_noalloc(self._h, n, float(dt), y_in.data_ptr(), y_out.data_ptr(), float(atol),
+                                             float(rtol), _stream_ptr(stream)), "radau_integrate_noalloc")
         return y_out
 
     def stats(self, per_state: bool = False) -> dict:

@@ -518,38 +518,57 @@ rk::Predictor *predictor_for(rk_mech *m, double dt) {
     return nullptr;
 }
 
+rk::Work handle_work(rk_mech *m) {
+    rk::Work w;
+    w.counters = m->counters;
+    w.queue = m->queue;
+    w.fb_list = m->fb_list;
+    w.bins = m->bins;
+    w.order = m->order;
+    w.hist = m->hist;
+    w.proxy = m->proxy_scratch;
+    w.lane = m->scratch;
+    w.slab = m->block_slab;
+    w.allow_predictor = true;
+    return w;
+}
+
 // Enqueue the flag clear, the optional cost binning and the integrator.
+// w names the device buffers: the handle's workspaces, or the caller-free
+// static array of the no-allocation entry (no predictor, no bins there).
 hipError_t launch_integrator(rk_mech *m, const rk::RadauParams &p, int64_t n, const double *yin, double *yout,
-                             double atol, double rtol, int variant, int nbins, int gpct, hipStream_t st) {
-    hipError_t e = rk::launch_zero_i32(m->counters + (size_t)rk::C_FLAGS * n, n, st);
+                             double atol, double rtol, int variant, int nbins, int gpct, hipStream_t st,
+                             const rk::Work &w) {
+    hipError_t e = rk::launch_zero_i32(w.counters + (size_t)rk::C_FLAGS * n, n, st);
     if (e != hipSuccess) return e;
     const int *order = nullptr;
     const double *pred = nullptr;
-    rk::Predictor *pr = (variant == 1 || variant == 2) ? predictor_for(m, p.dt) : nullptr;
+    rk::Predictor *pr = (w.allow_predictor && (variant == 1 || variant == 2)) ? predictor_for(m, p.dt) : nullptr;
     if (pr) {
         e = pr->ensure(n);
         if (e != hipSuccess) return e;
         // network inference; with bins, the key is the predicted step count
-        e = rk::launch_predictor(*pr, n, yin, p.dt, atol, rtol, nbins, nbins > 0 ? m->bins : nullptr, st);
+        e = rk::launch_predictor(*pr, n, yin, p.dt, atol, rtol, nbins, nbins > 0 ? w.bins : nullptr, st);
         if (e != hipSuccess) return e;
         pred = pr->pred;
         if (nbins > 0) {
-            e = rk::launch_sort_bins(m->bins, n, nbins, m->order, m->hist, st);
+            e = rk::launch_sort_bins(w.bins, n, nbins, w.order, w.hist, st);
             if (e != hipSuccess) return e;
-            order = m->order;
+            order = w.order;
         }
     } else if (nbins > 0) {
-        e = rk::launch_binning(m->dev, n, yin, p.dt, atol, rtol, nbins, m->bins, m->order, m->hist, m->proxy_scratch, st);
+        e = rk::launch_binning(m->dev, n, yin, p.dt, atol, rtol, nbins, w.bins, w.order, w.hist, w.proxy, st);
         if (e != hipSuccess) return e;
-        order = m->order;
+        order = w.order;
     }
     m->last_nbins = nbins;
+    m->last_order = nbins > 0 ? w.order : nullptr;
     if (variant == 3) {
         // one block per state; the slabs were sized for block_blocks blocks
         const int64_t cap = std::max<int64_t>(1, (int64_t)m->block_blocks * gpct / 100);
         const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(n, cap));
         m->last_grid = grid;
-        return rk::launch_radau_block(m->dev, p, n, yin, yout, m->counters, m->queue, order, m->block_slab, grid, st);
+        return rk::launch_radau_block(m->dev, p, n, yin, yout, w.counters, w.queue, order, w.slab, grid, st);
     }
     if (variant == 1 || variant == 2) {
         if (m->group_blocks == 0) m->group_blocks = rk::group_max_blocks(m->dev);
@@ -558,11 +577,11 @@ hipError_t launch_integrator(rk_mech *m, const rk::RadauParams &p, int64_t n, co
         const int64_t cap = std::max<int64_t>(1, (int64_t)m->group_blocks * gpct / 100);
         const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(need, cap));
         m->last_grid = grid;
-        return rk::launch_radau_group(m->dev, p, n, yin, yout, m->counters, m->queue, m->fb_list, order, pred,
+        return rk::launch_radau_group(m->dev, p, n, yin, yout, w.counters, w.queue, w.fb_list, order, pred,
                                       variant == 2, grid, st);
     }
     m->last_grid = (int)((n + rk::kWave - 1) / rk::kWave);
-    return rk::launch_radau_lane(m->dev, p, n, yin, yout, m->scratch, m->counters, order, st);
+    return rk::launch_radau_lane(m->dev, p, n, yin, yout, w.lane, w.counters, order, st);
 }
 
 // Scheduling autotuner: times the integrator on the first min(n, 32768) states
@@ -596,7 +615,7 @@ int autotune(rk_mech *m, int64_t n, double dt, const double *yin, double atol, d
             if (variant == 0 && g != 100) continue;     // the lane kernel is not persistent
             for (int rep = 0; rep < 2; ++rep) {         // first run warms caches
                 e = hipEventRecord(m->ev0, st);
-                if (e == hipSuccess) e = launch_integrator(m, p, ms, ys, yo, atol, rtol, variant, b, g, st);
+                if (e == hipSuccess) e = launch_integrator(m, p, ms, ys, yo, atol, rtol, variant, b, g, st, handle_work(m));
                 if (e == hipSuccess) e = hipEventRecord(m->ev1, st);
                 if (e == hipSuccess) e = hipEventSynchronize(m->ev1);
                 if (e != hipSuccess) return hip_fail(e, "autotune trial");
@@ -612,6 +631,68 @@ int autotune(rk_mech *m, int64_t n, double dt, const double *yin, double atol, d
 }
 
 }  // namespace
+
+// The integration call on the handle's workspaces (w == nullptr: allocated
+// here as needed; predictor, bins and autotuner as set) or on caller-free
+// buffers (the no-allocation entry: wave and mixed variants only, input
+// order, cold starts, nothing allocated).
+int rk_integrate_common(rk_mech *m, int64_t n, double dt, const double *yin, double *yout, double atol, double rtol,
+                        void *stream, const rk::Work *w) {
+    if (!m) return fail(RK_EINVAL, "radau_integrate: NULL handle");
+    if (n < 0 || !(dt > 0.0) || !std::isfinite(dt) || !(atol >= 0.0) || !(rtol > 0.0))
+        return fail(RK_EINVAL, "radau_integrate: need n >= 0, dt > 0, atol >= 0, rtol > 0");
+    if (n > 0 && (!yin || !yout)) return fail(RK_EINVAL, "radau_integrate: NULL state pointer");
+    if (n > 0 && (!is_device_ptr(yin) || !is_device_ptr(yout)))
+        return fail(RK_EINVAL, "radau_integrate: state arrays must be device memory");
+    const bool group_ok = rk::group_supported(m->K + 1) && rk::group_lds_bytes(m->dev) <= 65536;
+    const bool block_ok = rk::block_supported(m->K + 1) && rk::block_lds_bytes(m->dev) <= 163840;
+    const int variant = m->variant >= 0 ? m->variant : (group_ok ? 1 : (block_ok ? 3 : 0));
+    if ((variant == 1 || variant == 2) && !group_ok)
+        return fail(RK_EINVAL, "radau_integrate: the wave and mixed variants need K + 1 <= 56");
+    if (variant == 3 && !block_ok)
+        return fail(RK_EINVAL, "radau_integrate: the block variant needs 57 <= K + 1 <= 153 and at most 160 KB of LDS per block");
+    if (w && variant != 1 && variant != 2)
+        return fail(RK_EINVAL, "radau_integrate_noalloc: only the wave and mixed variants (K + 1 <= 56)");
+    if (!w) {
+        int rc = ensure_workspace(m, std::max<int64_t>(n, 1));
+        if (rc == RK_OK && variant == 0) rc = ensure_lane_scratch(m, n);
+        if (rc == RK_OK && variant == 3) rc = ensure_block_slab(m);
+        if (rc != RK_OK) return rc;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    rk::RadauParams p{};
+    radau_constants(p);
+    p.dt = dt;
+    p.atol = atol;
+    p.rtol = rtol;
+    p.kmax = m->kmax;
+    p.nmax = m->nmax;
+    p.pred_use = m->pred_use;
+    p.force_fb = m->force_fb;
+    p.fp64_solves = m->fp64_solves;
+    p.kappa = m->kappa > 0.0 ? m->kappa : std::max(10.0 * 2.220446049250313e-16 / rtol, std::min(0.03, std::sqrt(rtol)));
+    p.h0 = m->h0 > 0.0 ? m->h0 : std::min(dt, 1e-6);
+    int nbins = w ? 0 : m->nbins, gpct = m->grid_pct;
+    if (!w && m->autotune && n >= 4096 && variant != 3) {   // block kernel: trials would cost seconds each
+        int rc2 = autotune(m, n, dt, yin, atol, rtol, st, p, variant, nbins, gpct);
+        if (rc2 != RK_OK) return rc2;
+    }
+    hipError_t e = hipEventRecord(m->ev0, st);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    const rk::Work work = w ? *w : handle_work(m);
+    e = launch_integrator(m, p, n, yin, yout, atol, rtol, variant, nbins, gpct, st, work);
+    if (e != hipSuccess) return hip_fail(e, "radau kernel launch");
+    e = hipEventRecord(m->ev1, st);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    m->last_n = n;
+    m->last_counters = work.counters;
+    m->last_stream = st;
+    m->have_run = true;
+    return RK_OK;
+}
+
+
+int rk_fail(int code, const char *msg) { return fail(code, msg); }
 
 // =============================================================================
 // C ABI
@@ -742,51 +823,7 @@ int radau_set_option(rk_mech *m, const char *key, const char *value) {
 
 int radau_integrate(rk_mech *m, int64_t n, double dt, const double *yin, double *yout, double atol, double rtol,
                     void *stream) {
-    if (!m) return fail(RK_EINVAL, "radau_integrate: NULL handle");
-    if (n < 0 || !(dt > 0.0) || !std::isfinite(dt) || !(atol >= 0.0) || !(rtol > 0.0))
-        return fail(RK_EINVAL, "radau_integrate: need n >= 0, dt > 0, atol >= 0, rtol > 0");
-    if (n > 0 && (!yin || !yout)) return fail(RK_EINVAL, "radau_integrate: NULL state pointer");
-    if (n > 0 && (!is_device_ptr(yin) || !is_device_ptr(yout)))
-        return fail(RK_EINVAL, "radau_integrate: state arrays must be device memory");
-    const bool group_ok = rk::group_supported(m->K + 1) && rk::group_lds_bytes(m->dev) <= 65536;
-    const bool block_ok = rk::block_supported(m->K + 1) && rk::block_lds_bytes(m->dev) <= 163840;
-    const int variant = m->variant >= 0 ? m->variant : (group_ok ? 1 : (block_ok ? 3 : 0));
-    if ((variant == 1 || variant == 2) && !group_ok)
-        return fail(RK_EINVAL, "radau_integrate: the wave and mixed variants need K + 1 <= 56");
-    if (variant == 3 && !block_ok)
-        return fail(RK_EINVAL, "radau_integrate: the block variant needs 57 <= K + 1 <= 153 and at most 160 KB of LDS per block");
-    int rc = ensure_workspace(m, std::max<int64_t>(n, 1));
-    if (rc == RK_OK && variant == 0) rc = ensure_lane_scratch(m, n);
-    if (rc == RK_OK && variant == 3) rc = ensure_block_slab(m);
-    if (rc != RK_OK) return rc;
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    rk::RadauParams p{};
-    radau_constants(p);
-    p.dt = dt;
-    p.atol = atol;
-    p.rtol = rtol;
-    p.kmax = m->kmax;
-    p.nmax = m->nmax;
-    p.pred_use = m->pred_use;
-    p.force_fb = m->force_fb;
-    p.fp64_solves = m->fp64_solves;
-    p.kappa = m->kappa > 0.0 ? m->kappa : std::max(10.0 * 2.220446049250313e-16 / rtol, std::min(0.03, std::sqrt(rtol)));
-    p.h0 = m->h0 > 0.0 ? m->h0 : std::min(dt, 1e-6);
-    int nbins = m->nbins, gpct = m->grid_pct;
-    if (m->autotune && n >= 4096 && variant != 3) {   // block kernel: trials would cost seconds each
-        int rc2 = autotune(m, n, dt, yin, atol, rtol, st, p, variant, nbins, gpct);
-        if (rc2 != RK_OK) return rc2;
-    }
-    hipError_t e = hipEventRecord(m->ev0, st);
-    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
-    e = launch_integrator(m, p, n, yin, yout, atol, rtol, variant, nbins, gpct, st);
-    if (e != hipSuccess) return hip_fail(e, "radau kernel launch");
-    e = hipEventRecord(m->ev1, st);
-    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
-    m->last_n = n;
-    m->last_stream = st;
-    m->have_run = true;
-    return RK_OK;
+    return rk_integrate_common(m, n, dt, yin, yout, atol, rtol, stream, nullptr);
 }
 
 int stats_get(rk_mech *m, rk_stats *out, int32_t *steps, int32_t *status) {
@@ -801,7 +838,7 @@ int stats_get(rk_mech *m, rk_stats *out, int32_t *steps, int32_t *status) {
     out->n_states = n;
     if (n == 0) return RK_OK;
     std::vector<int32_t> c((size_t)n * rk::kNumCounters);
-    e = hipMemcpy(c.data(), m->counters, c.size() * sizeof(int32_t), hipMemcpyDeviceToHost);
+    e = hipMemcpy(c.data(), m->last_counters, c.size() * sizeof(int32_t), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpy of counters");
     const int32_t *st = &c[(size_t)rk::C_STATUS * n];
     const int32_t *ns = &c[(size_t)rk::C_NSTEP * n];
@@ -846,9 +883,9 @@ int stats_get(rk_mech *m, rk_stats *out, int32_t *steps, int32_t *status) {
     hist(32, out->d_hist32, &out->d_mean32);
     // the same measure over the work-queue order the integrator drew states in
     // (how well the cost bins put states of equal step counts next to each other)
-    if (m->last_nbins > 0 && m->order) {
+    if (m->last_nbins > 0 && m->last_order) {
         std::vector<int32_t> ord((size_t)n), qs((size_t)n);
-        e = hipMemcpy(ord.data(), m->order, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToHost);
+        e = hipMemcpy(ord.data(), m->last_order, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToHost);
         if (e != hipSuccess) return hip_fail(e, "hipMemcpy of the queue order");
         for (int64_t q = 0; q < n; ++q) qs[q] = ns[ord[q]];
         const int32_t *keep = ns;

@@ -114,6 +114,19 @@ hipError_t launch_radau_block(const DevMech &m, const RadauParams &p, int64_t n,
                               int32_t *counters, int *queue, const int *order, double *slab, int grid, hipStream_t st);
 size_t group_lds_bytes(const DevMech &m);   // per block
 
+// Device buffers of one integration call (rk_api.cpp): the handle's
+// workspaces, or the static array of the no-allocation entry (rk_noalloc.hip).
+struct Work {
+    int32_t *counters = nullptr;   // [kNumCounters][n]
+    int *queue = nullptr;          // four queue heads / counts
+    int *fb_list = nullptr;        // [n] states handed from the FP32 to the FP64 pass
+    int *bins = nullptr, *order = nullptr, *hist = nullptr;
+    double *proxy = nullptr;       // proxy-key evaluation scratch
+    double *lane = nullptr;        // lane-kernel working set
+    double *slab = nullptr;        // block-kernel Jacobian slabs
+    bool allow_predictor = false;
+};
+
 // Predictor network (rk_mlp.hip): FP32 masters, BF16 copy used in products.
 struct Mlp {
     std::vector<int> dims;
@@ -200,7 +213,16 @@ struct rk_mech {
     double *block_slab = nullptr;   // per-block Jacobian slabs of the block kernel
     size_t block_slab_cap = 0;      // doubles
     int64_t last_n = 0;
+    int32_t *last_counters = nullptr;   // counters of the last call (handle or static array)
+    int *last_order = nullptr;          // its queue order (nullptr: input order)
     hipStream_t last_stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool have_run = false;
 };
+
+// integration call shared by radau_integrate (w == nullptr) and the
+// no-allocation entry (w = its static buffers)
+int rk_integrate_common(rk_mech *m, int64_t n, double dt, const double *yin, double *yout, double atol, double rtol,
+                        void *stream, const rk::Work *w);
+// record an error message for rk_last_error (thread-local) and return code
+int rk_fail(int code, const char *msg);
