@@ -37,7 +37,8 @@ def build(force: bool = False) -> str:
 
 class Opts(ctypes.Structure):
     _fields_ = [("kmax", ctypes.c_int), ("kappa", ctypes.c_double), ("h0", ctypes.c_double),
-                ("nmax", ctypes.c_int), ("untransformed", ctypes.c_int), ("isothermal", ctypes.c_int)]
+                ("nmax", ctypes.c_int), ("untransformed", ctypes.c_int), ("isothermal", ctypes.c_int),
+                ("fd_jac", ctypes.c_int)]
 
 
 class Result(ctypes.Structure):
@@ -73,6 +74,9 @@ def lib():
         L.or_jac.argtypes = [ctypes.c_void_p, dp, ctypes.c_double, dp]
         L.or_jac_iso.argtypes = [ctypes.c_void_p, dp, ctypes.c_double, dp]
         L.or_jac_cs.argtypes = [ctypes.c_void_p, dp, ctypes.c_double, dp]
+        L.or_jac_fd.argtypes = [ctypes.c_void_p, dp, ctypes.c_double, dp, ctypes.c_double, ctypes.c_double,
+                                ctypes.c_double, dp]
+        L.or_jac_fd_quadratic.argtypes = [ctypes.c_int, dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
         L.or_radau_constants.argtypes = [dp] * 7
         L.or_default_opts.argtypes = [ctypes.POINTER(Opts)]
         L.or_integrate_batch.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, dp, dp,
@@ -149,6 +153,14 @@ class Mech:
         y = np.ascontiguousarray(y, dtype=np.float64)
         J = np.zeros((self.N, self.N))
         (lib().or_jac_iso if isothermal else lib().or_jac)(self.h, _p(y), P, _p(J))
+        return J
+
+    def jac_fd(self, y: np.ndarray, P: float, h: float, atol: float = 1e-10, rtol: float = 1e-6) -> np.ndarray:
+        """First-order forward-difference Jacobian (CVODE-style increments)."""
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        f0 = self.rhs(y, P)
+        J = np.zeros((self.N, self.N))
+        lib().or_jac_fd(self.h, _p(y), P, _p(f0), h, atol, rtol, _p(J))
         return J
 
     def jac_cs(self, y: np.ndarray, P: float) -> np.ndarray:
@@ -241,3 +253,13 @@ def integrate_linear(M: np.ndarray, y0: np.ndarray, dt: float, atol: float, rtol
     lib().or_integrate_linear(N, _p(M), _p(y0), dt, atol, rtol, ctypes.byref(o), _p(out), ctypes.byref(res),
                               _p(hrec), cap)
     return out, res, hrec[:min(res.naccept, cap)].copy()
+
+
+def jac_fd_quadratic(A: np.ndarray, y: np.ndarray, h: float, atol: float, rtol: float) -> np.ndarray:
+    """The oracle's forward-difference Jacobian of f_i(y) = sum_j A_ij y_j^2."""
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    N = y.shape[0]
+    J = np.zeros((N, N))
+    lib().or_jac_fd_quadratic(N, _p(A), _p(y), h, atol, rtol, _p(J))
+    return J

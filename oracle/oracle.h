@@ -60,6 +60,7 @@ typedef struct {
     int nmax;                 /* step attempts limit (default 100000) */
     int untransformed;        /* 1: solve the 3N x 3N Newton system directly */
     int isothermal;           /* 1: dT/dt = 0 (used only to relax burnt templates) */
+    int fd_jac;               /* 1: first-order forward-difference Jacobian (Sec. 3.4) */
 } or_opts;
 
 typedef struct {
@@ -73,6 +74,17 @@ typedef struct {
 int  or_mech_load(const char *path, or_mech **out);
 void or_mech_free(or_mech *m);
 int  or_mech_dims(const or_mech *m, int *K, int *R, int *E);
+
+/* First-order forward-difference Jacobian of the chemistry right-hand side
+ * (the alternative to the analytical Jacobian compared in Sec. 3.4), with
+ * CVODE's dense difference-quotient increments: column j uses
+ * inc_j = max(sqrt(u) |y_j|, m w_j), w_j = atol + rtol |y_j|,
+ * m = 1000 |h| u N ||f(y)||_w (||.||_w the weighted RMS norm; m = 1 when
+ * f(y) = 0).  J is row-major N x N; f0 = f(y). */
+void or_jac_fd(const or_mech *m, const double *y, double P, const double *f0, double h, double atol, double rtol,
+               double *J);
+/* the same rule applied to f_i(y) = sum_j A_ij y_j^2 (tests of the increments) */
+void or_jac_fd_quadratic(int N, const double *A, const double *y, double h, double atol, double rtol, double *J);
 
 /* default options */
 void or_default_opts(or_opts *o);

@@ -157,6 +157,7 @@ void or_radau_constants(double *A, double *c, double *b, double *ev, double *T, 
 
 void or_default_opts(or_opts *o) {
     o->kmax = 7; o->kappa = 0.0; o->h0 = 0.0; o->nmax = 100000; o->untransformed = 0; o->isothermal = 0;
+    o->fd_jac = 0;
 }
 
 /* ------------------------------------------------------------------------- */
@@ -168,6 +169,32 @@ typedef struct {
     void (*jac)(void *ctx, const double *y, double *J);
     void *ctx;
 } problem;
+
+/* First-order forward differences of f around y (Sec. 3.4's finite-difference
+ * Jacobian), increments by CVODE's dense difference-quotient rule: the larger
+ * of sqrt(u) |y_j| and a floor proportional to the step size, the weighted
+ * norm of f(y) and the error weight of component j.  f0 = f(y); work: 2 N. */
+static void fd_jacobian(const problem *pb, const double *y, const double *f0, double h, double atol, double rtol,
+                        double *J, double *work) {
+    const int N = pb->N;
+    double *yp = work, *fp = work + N;
+    double fn = 0.0;
+    for (int i = 0; i < N; ++i) {
+        const double w = atol + rtol * fabs(y[i]);
+        fn += (f0[i] / w) * (f0[i] / w);
+    }
+    fn = sqrt(fn / N);
+    const double minc = fn != 0.0 ? 1000.0 * fabs(h) * UROUND * N * fn : 1.0;
+    memcpy(yp, y, sizeof(double) * N);
+    for (int j = 0; j < N; ++j) {
+        const double w = atol + rtol * fabs(y[j]);
+        const double inc = fmax(sqrt(UROUND) * fabs(y[j]), minc * w);
+        yp[j] = y[j] + inc;
+        pb->f(pb->ctx, yp, fp);
+        yp[j] = y[j];
+        for (int i = 0; i < N; ++i) J[i * N + j] = (fp[i] - f0[i]) / inc;
+    }
+}
 
 /* scaled RMS norm over n entries with weights sc (period N) */
 static double rms(const double *v, const double *sc, int n, int N) {
@@ -206,6 +233,7 @@ static int radau_core(const problem *pb, double dt, double *y, double atol, doub
     double *f0 = w, *sc = f0 + N, *Z = sc + N, *W = Z + N3, *F = W + N3, *dZ = F + N3, *dW = dZ + N3;
     double *Zs = dW + N3, *e = Zs + N3, *v = e + N, *ytmp = v + N, *rhs = ytmp + N;
     double complex *cz = malloc(sizeof(double complex) * N);
+    double *fdw = malloc(sizeof(double) * 2 * N);
 
     if (!finite_vec(y, N)) { res->status = OR_NONFINITE; goto done; }
 
@@ -221,7 +249,17 @@ static int radau_core(const problem *pb, double dt, double *y, double atol, doub
     enum { NEW_JAC, NEW_LU, SAME } action = NEW_JAC;
 
     for (;;) {
-        if (action == NEW_JAC) { pb->jac(pb->ctx, y, J); res->njev++; jac_fresh = 1; action = NEW_LU; }
+        if (action == NEW_JAC) {
+            if (o->fd_jac) {
+                fd_jacobian(pb, y, f0, h, atol, rtol, J, fdw);
+                res->nfev += N;
+            } else {
+                pb->jac(pb->ctx, y, J);
+            }
+            res->njev++;
+            jac_fresh = 1;
+            action = NEW_LU;
+        }
         if (action == NEW_LU) {
             for (size_t i = 0; i < nd; ++i) { E1[i] = -J[i]; E2[i] = -J[i]; }
             for (int i = 0; i < N; ++i) { E1[i * N + i] += k.g / h; E2[i * N + i] += (k.a + k.bt * I) / h; }
@@ -417,7 +455,7 @@ static int radau_core(const problem *pb, double dt, double *y, double atol, doub
         }
     }
 done:
-    free(J); free(E1); free(E2); free(p1); free(w); free(cz);
+    free(J); free(E1); free(E2); free(p1); free(w); free(cz); free(fdw);
     return res->status;
 }
 
@@ -433,6 +471,35 @@ static void chem_f(void *c, const double *y, double *f) {
 static void chem_j(void *c, const double *y, double *J) {
     chem_ctx *x = c;
     if (x->iso) or_jac_iso(x->m, y, x->P, J); else or_jac(x->m, y, x->P, J);
+}
+
+void or_jac_fd(const or_mech *m, const double *y, double P, const double *f0, double h, double atol, double rtol,
+               double *J) {
+    const int N = m->K + 1;
+    chem_ctx cx = { m, P, 0 };
+    problem pb = { N, chem_f, chem_j, &cx };
+    double *work = malloc(sizeof(double) * 2 * N);
+    fd_jacobian(&pb, y, f0, h, atol, rtol, J, work);
+    free(work);
+}
+
+typedef struct { int N; const double *A; } quad_ctx;
+static void quad_f(void *c, const double *y, double *f) {
+    quad_ctx *x = c;
+    for (int i = 0; i < x->N; ++i) {
+        double s = 0.0;
+        for (int j = 0; j < x->N; ++j) s += x->A[i * x->N + j] * y[j] * y[j];
+        f[i] = s;
+    }
+}
+
+void or_jac_fd_quadratic(int N, const double *A, const double *y, double h, double atol, double rtol, double *J) {
+    quad_ctx cx = { N, A };
+    problem pb = { N, quad_f, NULL, &cx };
+    double *work = malloc(sizeof(double) * 3 * N);
+    quad_f(&cx, y, work + 2 * N);
+    fd_jacobian(&pb, y, work + 2 * N, h, atol, rtol, J, work);
+    free(work);
 }
 
 static int integrate_rows(const or_mech *m, int64_t n, double dt, const double *y_in, double *y_out,
