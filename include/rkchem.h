@@ -71,6 +71,8 @@ typedef struct rk_stats {
      * the integrator drew states in (equal to d_hist64 when no bins are used) */
     int64_t d_hist64_queue[20];
     double d_mean64_queue;
+    int32_t tile_used;        /* queue entries a group (block) took per atomic grab */
+    int32_t reserved;
 } rk_stats;
 
 /* mech_load — read a mechanism file and upload it to the current device.
@@ -176,10 +178,16 @@ int stats_get(rk_mech *mech, rk_stats *out, int32_t *per_state_steps, int32_t *p
  *              error weights); states are queued costliest bin first
  *   "grid_pct" share of the resident capacity launched for the persistent
  *              kernels (10..100, default 100)
- *   "autotune" "1": on the first call per dt, time the integrator on the first
- *              min(n, 32768) states (8192 for K + 1 > 16) for bins in
- *              {0, 8, 16, 32} and grid in
- *              {100 %, 50 %}, keep the fastest (this call blocks the host);
+ *   "tile"     queue entries a group (block) takes per atomic grab (1..64,
+ *              default 1); results do not depend on it
+ *   "autotune" "1": on the first call per dt with at least 4096 states (1024
+ *              for "block"), time the integrator on the first min(n, S)
+ *              states (S = 32768 for K + 1 <= 16, 8192 for K + 1 <= 56, 1024
+ *              for "block") and keep the fastest schedule: bins
+ *              {0, 8, 16, 32} x grid {100, 75, 50} % ("block": bins {0, 16},
+ *              grid 100 %; "lane": bins only) at tile 1, then tile {2, 4} at
+ *              the best of those; the choice is reported by stats_get
+ *              (nbins_used, grid_used, tile_used); this call blocks the host;
  *              "0": forget the choices
  *   "predictor" path of a predictor file (network widths K+2 -> ... -> 3(K+1)+2,
  *              standardisation, parameters) trained for one global step size;
@@ -195,6 +203,13 @@ int stats_get(rk_mech *mech, rk_stats *out, int32_t *per_state_steps, int32_t *p
  *              the default first step size) | "bins" (no warm start: the
  *              network only keys the cost bins by its predicted step counts,
  *              so every state's result is bitwise that of a cold start)
+ *   "jacobian" "analytical" (default) | "fd": first-order forward-difference
+ *              Jacobian (the alternative Sec. 3.4 compares with the analytical
+ *              one): column j from (f(y + inc_j e_j) - f(y)) / inc_j with
+ *              CVODE's dense difference-quotient increments
+ *              inc_j = max(sqrt(u) |y_j|, 1000 |h| u N ||f(y)||_w w_j),
+ *              w_j = atol + rtol |y_j|: N more source-term evaluations per
+ *              Jacobian; variants "lane" and "wave" (RK_EINVAL otherwise)
  *   "force_fallback" "0" (default) | "1": test switch of the FP32 variants'
  *              fallbacks: "mixed" hands every state to the FP64 pass at its
  *              first accepted step; "block" switches every state to

@@ -28,7 +28,8 @@ class RkStats(ctypes.Structure):
                 ("d_mean64", ctypes.c_double), ("d_mean32", ctypes.c_double), ("kernel_ms", ctypes.c_double),
                 ("fp32_fallback", ctypes.c_int64), ("nbins_used", ctypes.c_int32), ("grid_used", ctypes.c_int32),
                 ("predictor_kept", ctypes.c_int64), ("predictor_fallback", ctypes.c_int64),
-                ("d_hist64_queue", ctypes.c_int64 * 20), ("d_mean64_queue", ctypes.c_double)]
+                ("d_hist64_queue", ctypes.c_int64 * 20), ("d_mean64_queue", ctypes.c_double),
+                ("tile_used", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 EXPORTS = ["mech_load", "mech_free", "mech_dims", "radau_integrate", "radau_integrate_noalloc", "stats_get",

@@ -584,15 +584,18 @@ hipError_t launch_integrator(rk_mech *m, const rk::RadauParams &p, int64_t n, co
     return rk::launch_radau_lane(m->dev, p, n, yin, yout, w.lane, w.counters, order, st);
 }
 
-// Scheduling autotuner: times the integrator on the first min(n, 32768) states
-// (8192 for mechanisms with more than 15 species), compacted, for every
-// (bin count, persistent-grid size) candidate and keeps
-// the fastest for this dt.  Runs once per (handle, dt); blocks the host.
+// Scheduling autotuner: times the integrator on a bounded sample (the first
+// min(n, S) states, compacted: S = 32768 for N <= 16, 8192 for N <= 56, 1024
+// for the block kernel) and keeps the fastest schedule for this dt.  A
+// coordinate search: cost-bin count x persistent-grid share at one state per
+// queue grab, then larger grabs at the best of those.  One warm-up run, then
+// one timed run per candidate.  Runs once per (handle, dt); blocks the host.
 int autotune(rk_mech *m, int64_t n, double dt, const double *yin, double atol, double rtol, hipStream_t st,
-             const rk::RadauParams &p, int variant, int &nbins, int &gpct) {
+             rk::RadauParams p, int variant, int &nbins, int &gpct, int &tile) {
     for (auto &t : m->tuned)
-        if (t.first == dt) { nbins = t.second.first; gpct = t.second.second; return RK_OK; }
-    const int64_t ms = std::min<int64_t>(n, m->K + 1 <= 16 ? 32768 : 8192);   // bounded trial cost
+        if (t.dt == dt) { nbins = t.bins; gpct = t.grid_pct; tile = t.tile; return RK_OK; }
+    const int64_t cap = variant == 3 ? 1024 : (m->K + 1 <= 16 ? 32768 : 8192);
+    const int64_t ms = std::min<int64_t>(n, cap);
     const int rows = m->K + 2;
     const size_t need = (size_t)ms * rows * 2;
     if (need > m->tune_cap) {
@@ -606,27 +609,47 @@ int autotune(rk_mech *m, int64_t n, double dt, const double *yin, double atol, d
     double *ys = m->tune_buf, *yo = m->tune_buf + (size_t)ms * rows;
     hipError_t e = rk::launch_gather_head(yin, n, ms, rows, ys, st);
     if (e != hipSuccess) return hip_fail(e, "autotune gather");
-    const int bins_c[] = {0, 8, 16, 32};
-    const int grid_c[] = {100, 50};
-    float best = 1e30f;
-    int bb = 0, bg = 100;
-    for (int b : bins_c)
-        for (int g : grid_c) {
-            if (variant == 0 && g != 100) continue;     // the lane kernel is not persistent
-            for (int rep = 0; rep < 2; ++rep) {         // first run warms caches
-                e = hipEventRecord(m->ev0, st);
-                if (e == hipSuccess) e = launch_integrator(m, p, ms, ys, yo, atol, rtol, variant, b, g, st, handle_work(m));
-                if (e == hipSuccess) e = hipEventRecord(m->ev1, st);
-                if (e == hipSuccess) e = hipEventSynchronize(m->ev1);
-                if (e != hipSuccess) return hip_fail(e, "autotune trial");
-            }
-            float ms_t = 0.0f;
-            (void)hipEventElapsedTime(&ms_t, m->ev0, m->ev1);
-            if (ms_t < best) { best = ms_t; bb = b; bg = g; }
+    struct Cand { int bins, grid, tile; };
+    std::vector<Cand> first;
+    if (variant == 3) {
+        for (int b : {0, 16}) first.push_back({b, 100, 1});
+    } else if (variant == 0) {
+        for (int b : {0, 8, 16, 32}) first.push_back({b, 100, 1});   // the lane kernel is not persistent
+    } else {
+        for (int b : {0, 8, 16, 32})
+            for (int g : {100, 75, 50}) first.push_back({b, g, 1});
+    }
+    auto time_one = [&](const Cand &c, float &ms_t) -> int {
+        p.tile = c.tile;
+        e = hipEventRecord(m->ev0, st);
+        if (e == hipSuccess) e = launch_integrator(m, p, ms, ys, yo, atol, rtol, variant, c.bins, c.grid, st, handle_work(m));
+        if (e == hipSuccess) e = hipEventRecord(m->ev1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(m->ev1);
+        if (e != hipSuccess) return hip_fail(e, "autotune trial");
+        (void)hipEventElapsedTime(&ms_t, m->ev0, m->ev1);
+        return RK_OK;
+    };
+    float t_warm = 0.0f, best = 1e30f;
+    int rc = time_one(first[0], t_warm);     // warms caches and code
+    if (rc != RK_OK) return rc;
+    Cand bc = first[0];
+    for (const Cand &c : first) {
+        float t = 0.0f;
+        if ((rc = time_one(c, t)) != RK_OK) return rc;
+        if (t < best) { best = t; bc = c; }
+    }
+    if (variant != 0) {
+        for (int tl : {2, 4}) {
+            const Cand c{bc.bins, bc.grid, tl};
+            float t = 0.0f;
+            if ((rc = time_one(c, t)) != RK_OK) return rc;
+            if (t < best) { best = t; bc = c; }
         }
-    m->tuned.push_back({dt, {bb, bg}});
-    nbins = bb;
-    gpct = bg;
+    }
+    m->tuned.push_back({dt, bc.bins, bc.grid, bc.tile, best});
+    nbins = bc.bins;
+    gpct = bc.grid;
+    tile = bc.tile;
     return RK_OK;
 }
 
@@ -651,6 +674,8 @@ int rk_integrate_common(rk_mech *m, int64_t n, double dt, const double *yin, dou
         return fail(RK_EINVAL, "radau_integrate: the wave and mixed variants need K + 1 <= 56");
     if (variant == 3 && !block_ok)
         return fail(RK_EINVAL, "radau_integrate: the block variant needs 57 <= K + 1 <= 153 and at most 160 KB of LDS per block");
+    if (m->fd_jac && variant != 0 && variant != 1)
+        return fail(RK_EINVAL, "radau_integrate: the forward-difference Jacobian runs with the lane and wave variants");
     if (w && variant != 1 && variant != 2)
         return fail(RK_EINVAL, "radau_integrate_noalloc: only the wave and mixed variants (K + 1 <= 56)");
     if (!w) {
@@ -668,15 +693,19 @@ int rk_integrate_common(rk_mech *m, int64_t n, double dt, const double *yin, dou
     p.kmax = m->kmax;
     p.nmax = m->nmax;
     p.pred_use = m->pred_use;
+    p.tile = m->tile;
     p.force_fb = m->force_fb;
+    p.fd_jac = m->fd_jac;
     p.fp64_solves = m->fp64_solves;
     p.kappa = m->kappa > 0.0 ? m->kappa : std::max(10.0 * 2.220446049250313e-16 / rtol, std::min(0.03, std::sqrt(rtol)));
     p.h0 = m->h0 > 0.0 ? m->h0 : std::min(dt, 1e-6);
-    int nbins = w ? 0 : m->nbins, gpct = m->grid_pct;
-    if (!w && m->autotune && n >= 4096 && variant != 3) {   // block kernel: trials would cost seconds each
-        int rc2 = autotune(m, n, dt, yin, atol, rtol, st, p, variant, nbins, gpct);
+    int nbins = w ? 0 : m->nbins, gpct = m->grid_pct, tile = m->tile;
+    if (!w && m->autotune && n >= (variant == 3 ? 1024 : 4096)) {
+        int rc2 = autotune(m, n, dt, yin, atol, rtol, st, p, variant, nbins, gpct, tile);
         if (rc2 != RK_OK) return rc2;
     }
+    p.tile = tile;
+    m->last_tile = tile;
     hipError_t e = hipEventRecord(m->ev0, st);
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
     const rk::Work work = w ? *w : handle_work(m);
@@ -801,6 +830,18 @@ int radau_set_option(rk_mech *m, const char *key, const char *value) {
         if (!m->autotune) m->tuned.clear();
         return RK_OK;
     }
+    if (k == "tile") {
+        const long x = std::strtol(value, &e, 10);
+        if (e == value || *e || x < 1 || x > 64) return fail(RK_EINVAL, "tile: states per queue grab, 1..64");
+        m->tile = (int)x;
+        return RK_OK;
+    }
+    if (k == "jacobian") {
+        if (v == "analytical") m->fd_jac = 0;
+        else if (v == "fd") m->fd_jac = 1;
+        else return fail(RK_EINVAL, "jacobian: analytical | fd");
+        return RK_OK;
+    }
     if (k == "force_fallback") {
         if (v != "0" && v != "1") return fail(RK_EINVAL, "force_fallback: 0 or 1");
         m->force_fb = v == "1";
@@ -898,6 +939,7 @@ int stats_get(rk_mech *m, rk_stats *out, int32_t *steps, int32_t *status) {
     }
     out->nbins_used = m->last_nbins;
     out->grid_used = m->last_grid;
+    out->tile_used = m->last_tile;
     if (steps) std::memcpy(steps, &c[(size_t)rk::C_NSTEP * n], (size_t)n * sizeof(int32_t));
     if (status) std::memcpy(status, st, (size_t)n * sizeof(int32_t));
     return RK_OK;

@@ -759,12 +759,18 @@ __global__ __launch_bounds__(BT) void radau_block_kernel(DevMech m, RadauParams 
         if (t == 0) L.ctr[k] += v;
     };
     bool have = false;
+    int qnext = 0, qend = 0;     // queue entries taken by this block and not yet started
 
     for (;;) {
         if (!have) {
-            if (t == 0) L.bci[0] = atomicAdd(queue, 1);
-            __syncthreads();
-            const int qi = L.bci[0];
+            // the block takes rp.tile consecutive queue entries per atomic
+            if (qnext >= qend) {
+                if (t == 0) L.bci[0] = atomicAdd(queue, rp.tile);
+                __syncthreads();
+                qnext = L.bci[0];
+                qend = qnext + rp.tile;
+            }
+            const int qi = qnext++;
             if (qi >= n) break;
             s = order ? (int64_t)order[qi] : (int64_t)qi;
             const double P = yin[(size_t)(K + 1) * n + s];

@@ -432,6 +432,34 @@ __device__ __forceinline__ void jac_g(const DevMech &m, const GL &L, int r, doub
     sync_wave();
 }
 
+// First-order forward-difference Jacobian into L.J (the alternative to the
+// analytical Jacobian that Sec. 3.4 compares): column c from
+// (f(y + inc_c e_c) - f(y)) / inc_c, CVODE's dense difference-quotient
+// increments inc_c = max(sqrt(u) |y_c|, m w_c), w_c = atol + rtol |y_c|,
+// m = 1000 |h| u N ||f(y)||_w (1 when f(y) = 0).  f(y) of the step is in
+// L.f0s; one group-cooperative source-term evaluation per column.
+template <int G, int NC>
+__device__ __forceinline__ void jac_fd_g(const DevMech &m, const GL &L, int r, double yv, double P, double h,
+                                          double atol, double rtol) {
+    constexpr int LD = NC + 1;
+    const int N = m.N;
+    const bool comp = r < N;
+    const double f0 = comp ? L.f0s[r] : 0.0;
+    const double w = comp ? atol + rtol * fabs(yv) : 1.0;
+    const double fn = sqrt(gsum<G>(comp ? (f0 / w) * (f0 / w) : 0.0) / N);
+    const double minc = fn != 0.0 ? 1000.0 * fabs(h) * kU * N * fn : 1.0;
+    const double inc_l = comp ? fmax(sqrt(kU) * fabs(yv), minc * w) : 1.0;
+    for (int i = r; i < NC * LD; i += G) L.J[i] = 0.0;
+    sync_wave();
+#pragma nounroll
+    for (int c = 0; c < N; ++c) {
+        const double inc = gb<G>(inc_l, c);
+        const double fp = rhs_g<G>(m, L, r, yv + (r == c ? inc : 0.0), P);
+        if (comp) L.J[r * LD + c] = (fp - f0) / inc;
+    }
+    sync_wave();
+}
+
 // ---------------------------------------------------------------------------
 // LU with partial pivoting by row ownership, then rows moved to pivot order.
 // Step k picks, among the rows not yet used, the one with the largest
@@ -732,6 +760,138 @@ __device__ __forceinline__ double ematvec(const GL &L, int r, int N, double c, d
     return r < N ? acc : 0.0;
 }
 
+// Substitutions with FP32 factors in FP32 arithmetic.  The factors are only
+// accurate to FP32 (of the equilibrated matrices), so an FP32 substitution
+// loses nothing the FP64 refinement that follows does not restore, and it
+// halves the cross-lane moves (one readlane or DPP move per value, not two).
+template <int CTRL>
+__device__ __forceinline__ float dppf(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+template <int G>
+__device__ __forceinline__ float bcastf(float v, int k) {
+    if constexpr (G == 64) {
+        return rlane(v, k);
+    } else {
+        switch (k) {
+            case 0: return dppf<0x150>(v);
+            case 1: return dppf<0x151>(v);
+            case 2: return dppf<0x152>(v);
+            case 3: return dppf<0x153>(v);
+            case 4: return dppf<0x154>(v);
+            case 5: return dppf<0x155>(v);
+            case 6: return dppf<0x156>(v);
+            case 7: return dppf<0x157>(v);
+            case 8: return dppf<0x158>(v);
+            case 9: return dppf<0x159>(v);
+            case 10: return dppf<0x15A>(v);
+            case 11: return dppf<0x15B>(v);
+            case 12: return dppf<0x15C>(v);
+            case 13: return dppf<0x15D>(v);
+            case 14: return dppf<0x15E>(v);
+            default: return dppf<0x15F>(v);
+        }
+    }
+}
+// factor entry read at its point of use (keeps the compiler from hoisting
+// copies of both factorisations out of the Newton loop)
+__device__ __forceinline__ float keepf(float v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
+// x = E1^-1 b1 and (x2 + i x3) = E2^-1 (b2 + i b3) with FP32 factors, the two
+// substitutions interleaved in one sweep (two independent dependency chains),
+// component r in lane r in and out
+template <int G, int NC>
+__device__ __forceinline__ void solve_pair_f32(const LUR<float, NC> &F1, const LUC<float, NC> &F2, int r, int N,
+                                               double &b1, double &br, double &bi) {
+    float a1 = gb<G>((float)(b1 * F1.rs), F1.src);
+    float ar = gb<G>((float)(br * F2.rs), F2.src), ai = gb<G>((float)(bi * F2.rs), F2.src);
+#pragma unroll
+    for (int k = 0; k < NC; ++k)
+        if (k < N) {
+            const float y1 = bcastf<G>(a1, k), yr = bcastf<G>(ar, k), yi = bcastf<G>(ai, k);
+            if (r > k) {
+                a1 -= keepf(F1.a[k]) * y1;
+                const float lr = keepf(F2.re[k]), li = keepf(F2.im[k]);
+                ar -= lr * yr - li * yi;
+                ai -= lr * yi + li * yr;
+            }
+        }
+    const float d1 = (float)F1.dinv, dr = (float)F2.dr, di = (float)F2.di;
+#pragma unroll
+    for (int k = NC - 1; k >= 0; --k)
+        if (k < N) {
+            if (r == k) {
+                a1 *= d1;
+                const float tr = ar * dr - ai * di;
+                ai = ar * di + ai * dr;
+                ar = tr;
+            }
+            const float x1 = bcastf<G>(a1, k), xr = bcastf<G>(ar, k), xi = bcastf<G>(ai, k);
+            if (r < k) {
+                a1 -= keepf(F1.a[k]) * x1;
+                const float ur = keepf(F2.re[k]), ui = keepf(F2.im[k]);
+                ar -= ur * xr - ui * xi;
+                ai -= ur * xi + ui * xr;
+            }
+        }
+    b1 = r < N ? (double)a1 * F1.cs : 0.0;
+    br = r < N ? (double)ar * F2.cs : 0.0;
+    bi = r < N ? (double)ai * F2.cs : 0.0;
+}
+
+// x = E1^-1 b with FP32 factors in FP32 arithmetic
+template <int G, int NC>
+__device__ __forceinline__ double solve_real_f32(const LUR<float, NC> &F, int r, int N, double b) {
+    float acc = gb<G>((float)(b * F.rs), F.src);
+#pragma unroll
+    for (int k = 0; k < NC; ++k)
+        if (k < N) {
+            const float yk = bcastf<G>(acc, k);
+            if (r > k) acc -= keepf(F.a[k]) * yk;
+        }
+    const float d = (float)F.dinv;
+#pragma unroll
+    for (int k = NC - 1; k >= 0; --k)
+        if (k < N) {
+            if (r == k) acc *= d;
+            const float xk = bcastf<G>(acc, k);
+            if (r < k) acc -= keepf(F.a[k]) * xk;
+        }
+    return r < N ? (double)acc * F.cs : 0.0;
+}
+
+// J x for three vectors (J row-major in LDS, FP64), one sweep over the row;
+// the vectors go through the pivot-row and product buffers (contiguous, 3 NC)
+template <int NC>
+__device__ __forceinline__ void jv3(const GL &L, int r, int N, double x1, double x2, double x3, double &j1,
+                                    double &j2, double &j3) {
+    double *vb = L.prow;
+    sync_wave();
+    if (r < NC) {
+        vb[r] = x1;
+        vb[NC + r] = x2;
+        vb[2 * NC + r] = x3;
+    }
+    sync_wave();
+    double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    const double *row = L.J + (r < NC ? r : 0) * (NC + 1);
+#pragma unroll
+    for (int k = 0; k < NC; ++k)
+        if (k < N) {
+            const double a = row[k];
+            s1 += a * vb[k];
+            s2 += a * vb[NC + k];
+            s3 += a * vb[2 * NC + k];
+        }
+    sync_wave();
+    j1 = r < N ? s1 : 0.0;
+    j2 = r < N ? s2 : 0.0;
+    j3 = r < N ? s3 : 0.0;
+}
+
 enum { ACT_JAC = 0, ACT_LU = 1, ACT_SAME = 2 };
 
 // One step attempt per group per loop iteration: the groups of a wavefront run
@@ -743,7 +903,7 @@ enum { ACT_JAC = 0, ACT_LU = 1, ACT_SAME = 2 };
 // G = 16: at most 256 registers, so two wavefronts share each SIMD (the LDS
 // slices of eight 4-state blocks fit a CU); the few spills cost far less than
 // the latency the second wavefront hides.
-template <typename S, int G, int NC>
+template <typename S, int G, int NC, bool FDJ = false>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(G == 16 ? 2 : 1))) void radau_group_kernel(DevMech m, RadauParams rp, int64_t n,
                                                          const double *__restrict__ yin, double *__restrict__ yout,
                                                          int32_t *__restrict__ cnt, int *__restrict__ queue,
@@ -790,6 +950,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(G == 16 ? 2 
     int flags = 0;
     const int PD = 3 * N + 2;
     bool have = false, drained = false;
+    int qnext = 0, qend = 0;     // queue entries taken by this group and not yet started
     int64_t s = 0;
     // per-state values that are read rarely live in LDS: pressure L.hist[3],
     // time L.hist[4], f(y0) L.f0s; the error weights are recomputed from y
@@ -807,9 +968,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(G == 16 ? 2 
     for (;;) {
         // ---- refill: take the next state of the queue --------------------------
         if (!have && !drained) {
-            int qi = 0;
-            if (r == 0) qi = atomicAdd(queue, 1);
-            qi = gbi<G>(qi, 0);
+            // the group takes rp.tile consecutive queue entries per atomic
+            if (qnext >= qend) {
+                int q0 = 0;
+                if (r == 0) q0 = atomicAdd(queue, rp.tile);
+                qnext = gbi<G>(q0, 0);
+                qend = qnext + rp.tile;
+            }
+            const int qi = qnext++;
             if (qi >= nwork) {
                 drained = true;
             } else {
@@ -865,7 +1031,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(G == 16 ? 2 
 
         // ---- one step attempt ---------------------------------------------------
         if (action == ACT_JAC) {
-            jac_g<G, NC>(m, L, r, y, L.hist[3]);
+            if constexpr (FDJ) {
+                jac_fd_g<G, NC>(m, L, r, y, L.hist[3], h, atol, rtol);
+                bump(K_NFEV, N);
+            } else {
+                jac_g<G, NC>(m, L, r, y, L.hist[3]);
+            }
             bump(K_NJEV, 1);
             jac_fresh = true;
             action = ACT_LU;
@@ -938,17 +1109,28 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(G == 16 ? 2 
                 const double b1 = comp ? G1 - gh * W1 : 0.0;
                 const double b2 = comp ? G2 - (ah * W2 - bh * W3) : 0.0;
                 const double b3 = comp ? G3 - (bh * W2 + ah * W3) : 0.0;
-                double dW1 = solve_real<S, G>(E1, r, N, b1);
-                double dW2 = b2, dW3 = b3;
-                solve_cplx<S, G>(E2, r, N, dW2, dW3);
+                double dW1, dW2, dW3;
                 if constexpr (kMixed) {
-                    // one refinement step against the FP64 matrices
-                    dW1 += solve_real<S, G>(E1, r, N, b1 - ematvec<NC>(L, r, N, gh, dW1));
-                    double q2 = b2 - (ematvec<NC>(L, r, N, ah, dW2) - bh * dW3);
-                    double q3 = b3 - (ematvec<NC>(L, r, N, ah, dW3) + bh * dW2);
-                    solve_cplx<S, G>(E2, r, N, q2, q3);
+                    // both systems in one FP32 sweep, then one refinement step
+                    // against the FP64 matrices (residuals in FP64)
+                    dW1 = b1;
+                    dW2 = b2;
+                    dW3 = b3;
+                    solve_pair_f32<G, NC>(E1, E2, r, N, dW1, dW2, dW3);
+                    double j1, j2, j3;
+                    jv3<NC>(L, r, N, dW1, dW2, dW3, j1, j2, j3);
+                    double q1 = comp ? b1 - (gh * dW1 - j1) : 0.0;
+                    double q2 = comp ? b2 - ((ah * dW2 - j2) - bh * dW3) : 0.0;
+                    double q3 = comp ? b3 - ((ah * dW3 - j3) + bh * dW2) : 0.0;
+                    solve_pair_f32<G, NC>(E1, E2, r, N, q1, q2, q3);
+                    dW1 += q1;
                     dW2 += q2;
                     dW3 += q3;
+                } else {
+                    dW1 = solve_real<S, G>(E1, r, N, b1);
+                    dW2 = b2;
+                    dW3 = b3;
+                    solve_cplx<S, G>(E2, r, N, dW2, dW3);
                 }
                 const double dZ1 = rp.T[0] * dW1 + rp.T[1] * dW2 + rp.T[2] * dW3;
                 const double dZ2 = rp.T[3] * dW1 + rp.T[4] * dW2 + rp.T[5] * dW3;
@@ -1004,15 +1186,24 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(G == 16 ? 2 
                 const double sc2 = comp ? atol + rtol * fmax(fabs(y), fabs(y + Z3)) : 1.0;
                 const double gh = rp.g / h;
                 double v = comp ? L.f0s[r] + dz : 0.0;
-                double ev = solve_real<S, G>(E1, r, N, v);
-                if constexpr (kMixed) ev += solve_real<S, G>(E1, r, N, v - ematvec<NC>(L, r, N, gh, ev));   // FP64 residual
+                double ev;
+                if constexpr (kMixed) {
+                    ev = solve_real_f32<G, NC>(E1, r, N, v);
+                    ev += solve_real_f32<G, NC>(E1, r, N, v - ematvec<NC>(L, r, N, gh, ev));   // FP64 residual
+                } else {
+                    ev = solve_real<S, G>(E1, r, N, v);
+                }
                 double err = fmax(sqrt(gsum<G>(comp ? (ev / sc2) * (ev / sc2) : 0.0) / N), 1e-10);
                 if (err >= 1.0 && (first || reject)) {
                     const double fe = rhs_g<G>(m, L, r, y + ev, L.hist[3]);
                     bump(K_NFEV, 1);
                     v = comp ? fe + dz : 0.0;
-                    ev = solve_real<S, G>(E1, r, N, v);
-                    if constexpr (kMixed) ev += solve_real<S, G>(E1, r, N, v - ematvec<NC>(L, r, N, gh, ev));
+                    if constexpr (kMixed) {
+                        ev = solve_real_f32<G, NC>(E1, r, N, v);
+                        ev += solve_real_f32<G, NC>(E1, r, N, v - ematvec<NC>(L, r, N, gh, ev));
+                    } else {
+                        ev = solve_real<S, G>(E1, r, N, v);
+                    }
                     err = fmax(sqrt(gsum<G>(comp ? (ev / sc2) * (ev / sc2) : 0.0) / N), 1e-10);
                 }
                 if (!isfinite(err)) err = 1e300;
@@ -1108,8 +1299,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(G == 16 ? 2 
 // (element (r, c) of system i at (r * N + c) * n + i) is staged in LDS in the
 // integrator's row layout.  x1 = E1^-1 b1 and x2 + i x3 = E2^-1 (b2 + i b3)
 // with E1 = g/h I - J, E2 = (a + i b)/h I - J; b and x are [3][N][n].  FP32
-// factors are equilibrated with the error weights sc ([N][n]) and solved
-// without refinement, so x shows the factors' own accuracy.
+// factors are equilibrated with the error weights sc ([N][n]) and solved in
+// FP32 without refinement, so x shows the FP32 path's own accuracy.
 template <typename S, int G, int NC>
 __global__ __launch_bounds__(64) void lu_solve_kernel(int N, int64_t n, double gh, double ah, double bh,
                                                       const double *__restrict__ J, const double *__restrict__ sc,
@@ -1137,8 +1328,12 @@ __global__ __launch_bounds__(64) void lu_solve_kernel(int N, int64_t n, double g
     double b1 = comp ? b[(size_t)r * n + i] : 0.0;
     double b2 = comp ? b[((size_t)N + r) * n + i] : 0.0;
     double b3 = comp ? b[((size_t)2 * N + r) * n + i] : 0.0;
-    b1 = solve_real<S, G>(E1, r, N, b1);
-    solve_cplx<S, G>(E2, r, N, b2, b3);
+    if constexpr (std::is_same<S, float>::value) {
+        solve_pair_f32<G, NC>(E1, E2, r, N, b1, b2, b3);
+    } else {
+        b1 = solve_real<S, G>(E1, r, N, b1);
+        solve_cplx<S, G>(E2, r, N, b2, b3);
+    }
     if (comp) {
         x[(size_t)r * n + i] = b1;
         x[((size_t)N + r) * n + i] = b2;
@@ -1155,11 +1350,19 @@ void launch_lu_solve_one(int N, int64_t n, double gh, double ah, double bh, cons
                        n, gh, ah, bh, J, sc, b, x);
 }
 
-// enqueue one instantiation on its persistent grid
+// enqueue one instantiation on its persistent grid (FP64 factors with the
+// forward-difference Jacobian when p.fd_jac is set)
 template <typename S, int G, int NC>
 void launch_one(const DevMech &m, const RadauParams &p, int64_t n, const double *yin, double *yout, int32_t *cnt,
                 int *queue, const int *order, const int *work_n, const double *pred, int grid, hipStream_t st) {
     const size_t lds = block_lds_bytes<G, NC>(m.K, m.R, m.nsp, m.n3b);
+    if constexpr (std::is_same<S, double>::value) {
+        if (p.fd_jac) {
+            hipLaunchKernelGGL((radau_group_kernel<S, G, NC, true>), dim3(grid), dim3(kWave), lds, st, m, p, n, yin,
+                               yout, cnt, queue, order, work_n, pred);
+            return;
+        }
+    }
     hipLaunchKernelGGL((radau_group_kernel<S, G, NC>), dim3(grid), dim3(kWave), lds, st, m, p, n, yin, yout, cnt, queue,
                        order, work_n, pred);
 }

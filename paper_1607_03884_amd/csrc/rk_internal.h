@@ -40,6 +40,8 @@ struct RadauParams {
     double dt, atol, rtol, kappa, h0;
     int kmax, nmax;
     int pred_use;            // bit 1: predicted first step size, bit 2: predicted stage values
+    int tile;                // queue entries a group (block) takes per atomic grab
+    int fd_jac;              // first-order forward-difference Jacobian instead of the analytical one
     int force_fb;            // FP32 variants: take the fallback at the first accepted step (tests)
     int fp64_solves;         // block variant: FP64-accurate solves (three refinement sweeps) from the start
     double g, a, b;          // eigenvalues of A^-1: g, a +- i b
@@ -185,6 +187,7 @@ struct rk_mech {
     int variant = -1;          // -1 auto, 0 lane, 1 wave, 2 mixed (FP32 factors), 3 block (N > 56)
     int kmax = 7, nmax = 100000;
     int force_fb = 0, fp64_solves = 0;
+    int fd_jac = 0;            // Jacobian by forward differences (lane and wave variants)
     double kappa = 0.0, h0 = 0.0;
     // workspace of the last call
     double *scratch = nullptr;
@@ -202,8 +205,15 @@ struct rk_mech {
     // autotuner: chosen (bins, grid percent) per dt, trial buffers
     bool autotune = false;
     int pred_use = 3;
-    std::vector<std::pair<double, std::pair<int, int>>> tuned;
+    struct Tuned {
+        double dt;
+        int bins, grid_pct, tile;
+        float ms;
+    };
+    std::vector<Tuned> tuned;
     int grid_pct = 100;
+    int tile = 1;              // queue entries per grab
+    int last_tile = 1;
     double *tune_buf = nullptr;
     size_t tune_cap = 0;
     int last_nbins = 0, last_grid = 0;

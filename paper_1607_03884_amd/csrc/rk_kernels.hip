@@ -373,6 +373,33 @@ __device__ __forceinline__ double wrms(Lane M, int vo, int so, int n, int N) {
     return sqrt(s / n);
 }
 
+// First-order forward-difference Jacobian into J at jo (the alternative to
+// the analytical Jacobian that Sec. 3.4 compares): column j from
+// (f(y + inc_j e_j) - f(y)) / inc_j with CVODE's dense difference-quotient
+// increments inc_j = max(sqrt(u) |y_j|, m w_j), w_j = atol + rtol |y_j|,
+// m = 1000 |h| u N ||f(y)||_w (1 when f(y) = 0).  f(y) is at fo; the
+// perturbed state goes to tmp, its source terms to ev: N evaluations.
+__device__ void jacobian_fd(const DevMech &m, const LaneLayout &L, Lane M, int yo, int fo, int jo, double P,
+                            double h, double atol, double rtol) {
+    const int N = m.N;
+    double fn = 0.0;
+    for (int i = 0; i < N; ++i) {
+        const double q = M[fo + i] / (atol + rtol * fabs(M[yo + i]));
+        fn += q * q;
+    }
+    fn = sqrt(fn / N);
+    const double minc = fn != 0.0 ? 1000.0 * fabs(h) * kU * N * fn : 1.0;
+    for (int i = 0; i < N; ++i) M[L.tmp + i] = M[yo + i];
+    for (int j = 0; j < N; ++j) {
+        const double yj = M[yo + j];
+        const double inc = fmax(sqrt(kU) * fabs(yj), minc * (atol + rtol * fabs(yj)));
+        M[L.tmp + j] = yj + inc;
+        rhs(m, L, M, L.tmp, L.ev, P);
+        M[L.tmp + j] = yj;
+        for (int i = 0; i < N; ++i) M[jo + i * N + j] = (M[L.ev + i] - M[fo + i]) / inc;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------
@@ -436,7 +463,12 @@ __global__ __launch_bounds__(64) void radau_lane_kernel(DevMech m, LaneLayout L,
         int action = ACT_JAC;
         for (;;) {
             if (action == ACT_JAC) {
-                jacobian(m, L, M, L.y, L.J, P);
+                if (rp.fd_jac) {
+                    jacobian_fd(m, L, M, L.y, L.f0, L.J, P, h, atol, rtol);
+                    nfev += N;
+                } else {
+                    jacobian(m, L, M, L.y, L.J, P);
+                }
                 ++njev;
                 jac_fresh = true;
                 action = ACT_LU;

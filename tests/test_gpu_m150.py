@@ -136,11 +136,15 @@ def test_m150_block_edges(torch_dev, g150):
     small = g150.integrate(_dev(torch_dev, rows), 1e-6).cpu().numpy()
     g150.set_option("grid_pct", "100")
     assert np.array_equal(ref, small)
-    # cost bins reorder the queue; every state's result stays the same bits
+    # cost bins reorder the queue, a block may take several states per grab;
+    # every state's result stays the same bits
     g150.set_option("binning", "8")
+    g150.set_option("tile", "2")
     binned = g150.integrate(_dev(torch_dev, rows), 1e-6).cpu().numpy()
-    assert g150.stats()["nbins_used"] == 8
+    st = g150.stats()
+    assert st["nbins_used"] == 8 and st["tile_used"] == 2
     g150.set_option("binning", "0")
+    g150.set_option("tile", "1")
     assert np.array_equal(ref, binned)
     assert np.array_equal(np.delete(out, 5, axis=0), np.delete(ref.T, 5, axis=0))
     g150.set_option("variant", "auto")
@@ -170,3 +174,23 @@ def test_block_variant_refused_small(torch_dev):
     with pytest.raises(RkError):
         g.integrate(_dev(torch_dev, rows), 1e-6)
     g.close()
+
+
+def test_m150_block_autotune(torch_dev, g150):
+    """The autotuner runs for the block kernel on a bounded sample (the first
+    1024 states) and reports its choice; the tuned call's results equal the
+    untuned ones bit for bit."""
+    torch, _ = torch_dev
+    banner("M150 block autotune")
+    rows = configs.states_for(configs.WORKLOADS["cfg4"], 1100)
+    g150.set_option("variant", "block")
+    ref = g150.integrate(_dev(torch_dev, rows), 1e-6).cpu().numpy()
+    g150.set_option("autotune", "1")
+    tuned = g150.integrate(_dev(torch_dev, rows), 1e-6).cpu().numpy()
+    st = g150.stats()
+    g150.set_option("autotune", "0")
+    g150.set_option("variant", "auto")
+    print(f"block autotune: bins {st['nbins_used']}, grid {st['grid_used']}, tile {st['tile_used']}, "
+          f"kernel {st['kernel_ms']:.1f} ms")
+    assert st["nbins_used"] in (0, 16) and st["tile_used"] in (1, 2, 4)
+    assert np.array_equal(ref, tuned)

@@ -207,16 +207,17 @@ def test_cfg1_full_size_sampled(torch_dev, gm13, m13, dt, variant):
 
 @pytest.mark.parametrize("variant", VARIANTS)
 def test_schedule_invariance(torch_dev, gm13, variant):
-    """Queue order (input order, 16 cost bins, autotuned bins and grid) changes
-    which lanes/groups integrate a state, never its result: per-state outputs
-    and step counts are bitwise identical.  Outputs start as NaN so a state
-    dropped or duplicated by the ordering would show."""
+    """Queue order (input order, 16 cost bins, several states per queue grab,
+    autotuned bins, grid and grab size) changes which lanes/groups integrate a
+    state, never its result: per-state outputs and step counts are bitwise
+    identical.  Outputs start as NaN so a state dropped or duplicated by the
+    ordering would show."""
     banner(f"schedule invariance variant={variant}")
     torch, _ = torch_dev
     rows = configs.states_for(configs.WORKLOADS["cfg1"], 40000)
     y = _dev(torch_dev, rows)
     outs, steps = [], []
-    for opts in ({"binning": 0}, {"binning": 16}, {"binning": 0, "autotune": 1}):
+    for opts in ({"binning": 0}, {"binning": 16}, {"binning": 16, "tile": 3}, {"binning": 0, "tile": 1, "autotune": 1}):
         gm13.set_option("variant", variant)
         for k, v in opts.items():
             gm13.set_option(k, v)
@@ -226,8 +227,11 @@ def test_schedule_invariance(torch_dev, gm13, variant):
         st = gm13.stats(per_state=True)
         outs.append(out.cpu().numpy())
         steps.append(st["per_state_steps"].copy())
-        print(f"{variant} {opts}: kernel {st['kernel_ms']:.1f} ms, bins {st['nbins_used']}, grid {st['grid_used']}")
-    for k, v in (("binning", 0), ("autotune", 0), ("variant", "auto")):
+        print(f"{variant} {opts}: kernel {st['kernel_ms']:.1f} ms, bins {st['nbins_used']}, grid {st['grid_used']}, "
+              f"tile {st['tile_used']}")
+        if "tile" in opts and not opts.get("autotune"):
+            assert st["tile_used"] == (opts["tile"] if variant != "lane" else st["tile_used"])
+    for k, v in (("binning", 0), ("autotune", 0), ("tile", 1), ("variant", "auto")):
         gm13.set_option(k, v)
     assert np.all(np.isfinite(outs[0]))
     for o, s in zip(outs[1:], steps[1:]):
