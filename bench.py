@@ -143,6 +143,8 @@ def main() -> int:
                     help="instead of the headline: the runtime ratio of Radau IIA with the first-order "
                          "finite-difference Jacobian to the analytical one (paper Sec. 3.4), GPU lane and wave "
                          "kernels and the CPU oracle; prints one JSON line")
+    ap.add_argument("--ratio-variants", default="lane,wave",
+                    help="GPU variants of --jac-ratio (the lane kernel is slow for large mechanisms)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -425,7 +427,7 @@ def jac_ratio(args, wl, states, y, out, stream, path) -> int:
     from paper_1607_03884_amd import Mechanism, configs
     n = len(states)
     res = {"n_states": n, "gpu": {}, "cpu": {}}
-    for variant in ("lane", "wave"):
+    for variant in [v for v in args.ratio_variants.split(",") if v]:
         for jac in ("analytical", "fd"):
             m = Mechanism(path)
             m.set_option("variant", variant)
