@@ -16,7 +16,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle.so")
-SOURCES = ["mech.c", "chem.c", "radau.c"]
+SOURCES = ["mech.c", "chem.c", "radau.c", "ros.c"]
 
 OK, STEP_LIMIT, H_UNDERFLOW, NONFINITE = 0, 1, 2, 3
 
@@ -76,6 +76,11 @@ def lib():
         L.or_jac_cs.argtypes = [ctypes.c_void_p, dp, ctypes.c_double, dp]
         L.or_jac_fd.argtypes = [ctypes.c_void_p, dp, ctypes.c_double, dp, ctypes.c_double, ctypes.c_double,
                                 ctypes.c_double, dp]
+        L.or_integrate_rodas3.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, dp, dp, ctypes.c_double,
+                                          ctypes.c_double, ctypes.POINTER(Opts), ctypes.c_void_p, ctypes.c_int]
+        L.or_rodas3_fixed_steps.argtypes = [ctypes.c_void_p, dp, ctypes.c_double, ctypes.c_int, dp]
+        L.or_rodas3_linear_step.argtypes = [ctypes.c_int, dp, dp, ctypes.c_double, dp]
+        L.or_rodas3_table.argtypes = [dp, dp, dp, dp, dp]
         L.or_jac_fd_quadratic.argtypes = [ctypes.c_int, dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
         L.or_radau_constants.argtypes = [dp] * 7
         L.or_default_opts.argtypes = [ctypes.POINTER(Opts)]
@@ -187,6 +192,25 @@ class Mech:
                                  res.ctypes.data_as(ctypes.c_void_p), nthreads)
         return out, res
 
+    def integrate_rodas3(self, states: np.ndarray, dt: float, atol: float = 1e-10, rtol: float = 1e-6,
+                         opts: Optional[Opts] = None, nthreads: int = 0):
+        """Rodas3 (Rosenbrock) over [0, dt]; as integrate."""
+        st = np.ascontiguousarray(states, dtype=np.float64)
+        n = st.shape[0]
+        assert st.shape[1] == self.K + 2
+        out = np.zeros_like(st)
+        res = np.zeros(n, dtype=RESULT_DTYPE)
+        o = opts or default_opts()
+        lib().or_integrate_rodas3(self.h, n, dt, _p(st), _p(out), atol, rtol, ctypes.byref(o),
+                                  res.ctypes.data_as(ctypes.c_void_p), nthreads)
+        return out, res
+
+    def rodas3_fixed_steps(self, state: np.ndarray, dt: float, nsteps: int) -> np.ndarray:
+        st = np.ascontiguousarray(state, dtype=np.float64)
+        out = np.zeros(self.N)
+        lib().or_rodas3_fixed_steps(self.h, _p(st), dt, nsteps, _p(out))
+        return out
+
     def integrate_warm(self, states: np.ndarray, dt: float, hw: Optional[np.ndarray], zw: Optional[np.ndarray],
                        atol: float = 1e-10, rtol: float = 1e-6, opts: Optional[Opts] = None, nthreads: int = 0):
         """Integration with a per-state warm start for the first step attempt:
@@ -263,3 +287,19 @@ def jac_fd_quadratic(A: np.ndarray, y: np.ndarray, h: float, atol: float, rtol: 
     J = np.zeros((N, N))
     lib().or_jac_fd_quadratic(N, _p(A), _p(y), h, atol, rtol, _p(J))
     return J
+
+
+def rodas3_table():
+    g = np.zeros(1)
+    a, c = np.zeros(16), np.zeros(16)
+    m, e = np.zeros(4), np.zeros(4)
+    lib().or_rodas3_table(_p(g), _p(a), _p(c), _p(m), _p(e))
+    return dict(gamma=float(g[0]), a=a.reshape(4, 4), c=c.reshape(4, 4), m=m, e=e)
+
+
+def rodas3_linear_step(M: np.ndarray, y0: np.ndarray, h: float) -> np.ndarray:
+    M = np.ascontiguousarray(M, dtype=np.float64)
+    y0 = np.ascontiguousarray(y0, dtype=np.float64)
+    y1 = np.zeros_like(y0)
+    lib().or_rodas3_linear_step(len(y0), _p(M), _p(y0), h, _p(y1))
+    return y1

@@ -86,6 +86,18 @@ void or_jac_fd(const or_mech *m, const double *y, double P, const double *f0, do
 /* the same rule applied to f_i(y) = sum_j A_ij y_j^2 (tests of the increments) */
 void or_jac_fd_quadratic(int N, const double *A, const double *y, double h, double atol, double rtol, double *J);
 
+/* Rodas3 (Sandu et al.; four-stage L-stable Rosenbrock method of order 3 with
+ * an embedded order-2 estimate), the semi-implicit method the paper's
+ * conclusions recommend (Sec. 4): adaptive integration of n states over
+ * [0, dt] (same layout, options and result records as or_integrate_batch;
+ * nnewton = nnewtfail = 0), fixed steps, one step of a linear system, and
+ * its coefficient table (gamma, a and c 4x4 strictly lower, m, e). */
+int or_integrate_rodas3(const or_mech *m, int64_t n, double dt, const double *y_in, double *y_out, double atol,
+                        double rtol, const or_opts *o, or_result *res, int nthreads);
+int or_rodas3_fixed_steps(const or_mech *m, const double *y_row, double dt, int nsteps, double *y_out);
+int or_rodas3_linear_step(int N, const double *M, const double *y0, double h, double *y1);
+void or_rodas3_table(double *gamma, double *a, double *c, double *m, double *e);
+
 /* default options */
 void or_default_opts(or_opts *o);
 
