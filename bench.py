@@ -28,6 +28,13 @@ Forms (same library, same inputs):
                  bins (N = 57..153; the cooperative form for 150 species)
   block_fp64     block with FP64-accurate solves (three refinement sweeps
                  per solve from the first step)
+  block_learned  block with its queue binned by the MLP's predicted step
+                 counts (cold starts)
+  rodas3         the Rosenbrock method Rodas3 on the wavefront kernels (FP64,
+                 autotuned proxy bins): the semi-implicit alternative the
+                 paper recommends; it solves the same ODE to the same
+                 tolerances but follows its own steps, so its cold-oracle
+                 figure is the difference of two methods
 The headline form (--form) is timed over --steps steps; each comparison form
 gets one timed step (after a warm-up call when it autotunes).
 """
@@ -64,6 +71,8 @@ FORMS = {
     "lane": dict(variant="lane", binning=0, autotune=0, predictor=None),
     "block": dict(variant="block", binning=16, autotune=0, predictor=None),
     "block_fp64": dict(variant="block", binning=16, autotune=0, predictor=None, block_solves="fp64_accurate"),
+    "block_learned": dict(variant="block", binning=16, autotune=0, predictor="bins"),
+    "rodas3": dict(variant="wave", binning=0, autotune=1, predictor=None, method="rodas3"),
 }
 
 
@@ -190,8 +199,9 @@ def main() -> int:
         m = Mechanism(path)
         for k in ("variant", "binning", "autotune"):
             m.set_option(k, f[k])
-        if "block_solves" in f:
-            m.set_option("block_solves", f["block_solves"])
+        for key in ("block_solves", "method"):
+            if key in f:
+                m.set_option(key, f[key])
         if f["predictor"]:
             for dt in wl.dts:
                 m.set_option("predictor", predictor.path_for(wl.mech, dt))

@@ -196,13 +196,22 @@ int stats_get(rk_mech *mech, rk_stats *out, int32_t *per_state_steps, int32_t *p
  *              times a power of two) and stage values and keep them only if
  *              Newton converges on that attempt, else restart the state
  *              exactly as a cold start; with "binning" (or "autotune") the
- *              bin key becomes the predicted step count.  A file for another
- *              K is refused (RK_EINVAL).  "none" removes all predictors.
+ *              bin key becomes the predicted step count.  The "block" variant
+ *              uses the network for that bin key only (its states start
+ *              cold).  A file for another K is refused (RK_EINVAL).  "none"
+ *              removes all predictors.
  *   "predictor_use" "both" (default) | "h0" (predicted first step size only,
  *              stage values start at zero) | "z0" (predicted stage values with
  *              the default first step size) | "bins" (no warm start: the
  *              network only keys the cost bins by its predicted step counts,
  *              so every state's result is bitwise that of a cold start)
+ *   "method"   "radau" (default) | "rodas3": Rosenbrock integration instead
+ *              of Radau IIA, the semi-implicit direction the paper's
+ *              conclusions recommend (Sec. 4): Rodas3 (Sandu et al.; four
+ *              stages, order 3, embedded order 2, L-stable), one real FP64
+ *              factorisation of 1/(h gamma) I - J per step size, Jacobian at
+ *              every new y; variant "wave" (or "auto" for K + 1 <= 56) with
+ *              the analytical Jacobian, RK_EINVAL otherwise
  *   "jacobian" "analytical" (default) | "fd": first-order forward-difference
  *              Jacobian (the alternative Sec. 3.4 compares with the analytical
  *              one): column j from (f(y + inc_j e_j) - f(y)) / inc_j with

@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 SOURCES = ["rk_api.cpp", "rk_kernels.hip", "rk_group.hip", "rk_group16.hip", "rk_group64.hip", "rk_block.hip",
-           "rk_mlp.hip", "rk_pred.hip", "rk_noalloc.hip"]
+           "rk_mlp.hip", "rk_pred.hip", "rk_noalloc.hip", "rk_ros.hip"]
 # per-source extra flags: the block kernel's elimination loops (51 register
 # columns, nested) must unroll completely so every register index is constant
 EXTRA_FLAGS = {"rk_block.hip": ["-mllvm", "-pragma-unroll-threshold=400000"]}

@@ -543,7 +543,10 @@ hipError_t launch_integrator(rk_mech *m, const rk::RadauParams &p, int64_t n, co
     if (e != hipSuccess) return e;
     const int *order = nullptr;
     const double *pred = nullptr;
-    rk::Predictor *pr = (w.allow_predictor && (variant == 1 || variant == 2)) ? predictor_for(m, p.dt) : nullptr;
+    // the wavefront variants warm-start from the network and key bins by it; the
+    // block variant starts every state cold and uses the network for the bins only
+    const bool use_net = w.allow_predictor && (variant == 1 || variant == 2 || (variant == 3 && nbins > 0));
+    rk::Predictor *pr = use_net ? predictor_for(m, p.dt) : nullptr;
     if (pr) {
         e = pr->ensure(n);
         if (e != hipSuccess) return e;
@@ -572,6 +575,14 @@ hipError_t launch_integrator(rk_mech *m, const rk::RadauParams &p, int64_t n, co
     }
     if (variant == 1 || variant == 2) {
         if (m->group_blocks == 0) m->group_blocks = rk::group_max_blocks(m->dev);
+        if (p.method == 1) {
+            const int spb = rk::group_states_per_block(m->K + 1);
+            const int64_t need = (n + spb - 1) / spb;
+            const int64_t cap = std::max<int64_t>(1, (int64_t)m->group_blocks * gpct / 100);
+            const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(need, cap));
+            m->last_grid = grid;
+            return rk::launch_rodas3_group(m->dev, p, n, yin, yout, w.counters, w.queue, order, grid, st);
+        }
         const int spb = rk::group_states_per_block(m->K + 1);
         const int64_t need = (n + spb - 1) / spb;
         const int64_t cap = std::max<int64_t>(1, (int64_t)m->group_blocks * gpct / 100);
@@ -674,6 +685,8 @@ int rk_integrate_common(rk_mech *m, int64_t n, double dt, const double *yin, dou
         return fail(RK_EINVAL, "radau_integrate: the wave and mixed variants need K + 1 <= 56");
     if (variant == 3 && !block_ok)
         return fail(RK_EINVAL, "radau_integrate: the block variant needs 57 <= K + 1 <= 153 and at most 160 KB of LDS per block");
+    if (m->method == 1 && (variant != 1 || m->fd_jac))
+        return fail(RK_EINVAL, "radau_integrate: the Rodas3 method runs with the wave variant and the analytical Jacobian");
     if (m->fd_jac && variant != 0 && variant != 1)
         return fail(RK_EINVAL, "radau_integrate: the forward-difference Jacobian runs with the lane and wave variants");
     if (w && variant != 1 && variant != 2)
@@ -696,6 +709,7 @@ int rk_integrate_common(rk_mech *m, int64_t n, double dt, const double *yin, dou
     p.tile = m->tile;
     p.force_fb = m->force_fb;
     p.fd_jac = m->fd_jac;
+    p.method = m->method;
     p.fp64_solves = m->fp64_solves;
     p.kappa = m->kappa > 0.0 ? m->kappa : std::max(10.0 * 2.220446049250313e-16 / rtol, std::min(0.03, std::sqrt(rtol)));
     p.h0 = m->h0 > 0.0 ? m->h0 : std::min(dt, 1e-6);
@@ -834,6 +848,12 @@ int radau_set_option(rk_mech *m, const char *key, const char *value) {
         const long x = std::strtol(value, &e, 10);
         if (e == value || *e || x < 1 || x > 64) return fail(RK_EINVAL, "tile: states per queue grab, 1..64");
         m->tile = (int)x;
+        return RK_OK;
+    }
+    if (k == "method") {
+        if (v == "radau") m->method = 0;
+        else if (v == "rodas3") m->method = 1;
+        else return fail(RK_EINVAL, "method: radau | rodas3");
         return RK_OK;
     }
     if (k == "jacobian") {

@@ -174,6 +174,32 @@ __device__ __forceinline__ GL group_lds(double *base, int R) {
     return L;
 }
 
+// Stage the species lists (and, for 16-lane groups, the efficiencies) in the
+// block-shared LDS after the group slices, once per block.
+template <int G, int NC>
+__device__ __forceinline__ void stage_tables(const DevMech &m, double *smem, GL &L) {
+    const int K = m.K;
+    const SharedTables tb = shared_tables(G, K, m.nsp, m.n3b);
+    char *sh = reinterpret_cast<char *>(smem + (size_t)(kWave / G) * group_lds_doubles(NC, m.R));
+    int *so = reinterpret_cast<int *>(sh + tb.off_spoff);
+    int *sx = reinterpret_cast<int *>(sh + tb.off_sprx);
+    for (int i = threadIdx.x; i <= K; i += kWave) so[i] = m.sp_off[i];
+    for (int i = threadIdx.x; i < m.nsp; i += kWave) {
+        const int2 e = m.sp_rx[i];
+        sx[i] = (e.x << 4) | (e.y + 8);
+    }
+    L.spoff = so;
+    L.sprx = sx;
+    if constexpr (G == 16) {
+        double *se = reinterpret_cast<double *>(sh + tb.off_eff);
+        for (int i = threadIdx.x; i < m.n3b * K; i += kWave) se[i] = m.eff[i];
+        L.eff = se;
+    } else {
+        L.eff = m.eff;
+    }
+    sync_wave();
+}
+
 struct Thermo {
     double cp, h, s, dcp;
 };
@@ -916,28 +942,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(G == 16 ? 2 
     const int grp = threadIdx.x / G;
     const int N = m.N, K = m.K;
     GL L = group_lds<NC>(smem + (size_t)grp * group_lds_doubles(NC, m.R), m.R);
-    {
-        // stage the species lists (and, for 16-lane groups, the efficiencies) once per block
-        const SharedTables tb = shared_tables(G, K, m.nsp, m.n3b);
-        char *sh = reinterpret_cast<char *>(smem + (size_t)(kWave / G) * group_lds_doubles(NC, m.R));
-        int *so = reinterpret_cast<int *>(sh + tb.off_spoff);
-        int *sx = reinterpret_cast<int *>(sh + tb.off_sprx);
-        for (int i = threadIdx.x; i <= K; i += kWave) so[i] = m.sp_off[i];
-        for (int i = threadIdx.x; i < m.nsp; i += kWave) {
-            const int2 e = m.sp_rx[i];
-            sx[i] = (e.x << 4) | (e.y + 8);
-        }
-        L.spoff = so;
-        L.sprx = sx;
-        if constexpr (G == 16) {
-            double *se = reinterpret_cast<double *>(sh + tb.off_eff);
-            for (int i = threadIdx.x; i < m.n3b * K; i += kWave) se[i] = m.eff[i];
-            L.eff = se;
-        } else {
-            L.eff = m.eff;
-        }
-        sync_wave();
-    }
+    stage_tables<G, NC>(m, smem, L);
     const bool comp = r < N;                       // lane holds a state component
     const double dt = rp.dt, atol = rp.atol, rtol = rp.rtol, kappa = rp.kappa;
     const int kmax = rp.kmax;

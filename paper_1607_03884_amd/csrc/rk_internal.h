@@ -42,6 +42,7 @@ struct RadauParams {
     int pred_use;            // bit 1: predicted first step size, bit 2: predicted stage values
     int tile;                // queue entries a group (block) takes per atomic grab
     int fd_jac;              // first-order forward-difference Jacobian instead of the analytical one
+    int method;              // 0: Radau IIA, 1: Rodas3 (Rosenbrock; wave variant)
     int force_fb;            // FP32 variants: take the fallback at the first accepted step (tests)
     int fp64_solves;         // block variant: FP64-accurate solves (three refinement sweeps) from the start
     double g, a, b;          // eigenvalues of A^-1: g, a +- i b
@@ -106,6 +107,9 @@ hipError_t launch_lu_solve(int N, bool fp32, int64_t n, double gh, double ah, do
 int occupancy_group16(int NC, size_t lds);
 int occupancy_group64(int NC, size_t lds);
 hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t st);
+// Rodas3 (Rosenbrock) with the wavefront kernels' building blocks (rk_ros.hip)
+hipError_t launch_rodas3_group(const DevMech &m, const RadauParams &p, int64_t n, const double *yin, double *yout,
+                               int32_t *counters, int *queue, const int *order, int grid, hipStream_t st);
 // block-cooperative variant (rk_block.hip): one 512-lane block per state,
 // FP32 factors in registers, J in a per-block slab of global memory
 bool block_supported(int N);
@@ -188,6 +192,7 @@ struct rk_mech {
     int kmax = 7, nmax = 100000;
     int force_fb = 0, fp64_solves = 0;
     int fd_jac = 0;            // Jacobian by forward differences (lane and wave variants)
+    int method = 0;            // 0 Radau IIA, 1 Rodas3
     double kappa = 0.0, h0 = 0.0;
     // workspace of the last call
     double *scratch = nullptr;

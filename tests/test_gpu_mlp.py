@@ -11,7 +11,7 @@ from tests.parity import banner
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("dims", [[15, 128, 128, 44], [55, 128, 128, 164]])
+@pytest.mark.parametrize("dims", [[15, 128, 128, 44], [55, 128, 128, 164], [152, 256, 256, 455]])
 def test_forward_and_gradients_match_reference(dims):
     import torch
     banner(f"mlp forward/grad {dims}")
