@@ -167,11 +167,15 @@ int stats_get(rk_mech *mech, rk_stats *out, int32_t *per_state_steps, int32_t *p
  *              cooperates on one state, the per-block pattern for large
  *              mechanisms (Sec. 1.2, Sec. 4); iteration matrices equilibrated
  *              and factored in FP32 in registers, three lanes per row, J in
- *              FP64 in device memory; one refinement step per solve against
- *              the FP64 matrices; a state whose Newton iteration diverges twice
- *              in a row after its first accepted step continues with three
- *              refinement steps per solve (FP64-accurate solves) and counts
- *              in fp32_fallback; no predictor; persistent work queue).
+ *              FP64 in device memory; every solve refined against the FP64
+ *              matrices until the last correction is below 1e-8 in the error
+ *              weights (one to four sweeps; a correction larger than the
+ *              one before it ends the sweeps unapplied); a state whose
+ *              Newton iteration
+ *              diverges twice in a row after its first accepted step continues
+ *              with three to six sweeps per solve and
+ *              counts in fp32_fallback; the predictor keys its bins only;
+ *              persistent work queue).
  *              RK_EINVAL outside those sizes.
  *   "binning"  number of cost bins (0..64, default 0): one source-term
  *              evaluation per state gives the key ||dt f(y0)|| (RMS in the
@@ -224,11 +228,12 @@ int stats_get(rk_mech *mech, rk_stats *out, int32_t *per_state_steps, int32_t *p
  *              first accepted step; "block" switches every state to
  *              FP64-accurate solves after its first accepted step
  *   "block_solves" "fp32_refined" (default) | "fp64_accurate": the block
- *              variant refines every solve three times from the first step
- *              (FP64-accurate solves from FP32 factors and FP64 residuals;
- *              counted in fp32_fallback)
+ *              variant refines every solve at least three times from the first step
+ *              (FP64-accurate solves from FP32 factors and FP64 residuals
+ *              wherever cond(E) * 2^-24 is well below 1; counted in
+ *              fp32_fallback)
  *   "kmax"     max Newton iterations per step (default 7)
- *   "kappa"    Newton stopping constant (default max(10u/rtol, min(0.03, rtol^0.5)))
+ *   "kappa"    Newton stopping constant (0 = default: max(10u/rtol, min(0.03, rtol^0.5)))
  *   "nmax"     step-attempt limit per state (default 100000)
  *   "h0"       initial step size in seconds (default min(dt, 1e-6))
  * Returns RK_EINVAL for an unknown key or a malformed value. */

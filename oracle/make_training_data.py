@@ -7,6 +7,7 @@ first accepted Radau IIA step and the number of step attempts over the
 global step.  One file per mechanism and global step size.
 
 Run:  python -m oracle.make_training_data M13 200000
+      python -m oracle.make_training_data M150 16384 1e-4   (one global step size)
 Writes paper_1607_03884_amd/data/<mech>_train_dt<dt>.npz (not committed).
 """
 from __future__ import annotations
@@ -52,4 +53,5 @@ def make(mech: str, n: int, dts=(configs.DT_SMALL, configs.DT_LARGE), nthreads: 
 
 
 if __name__ == "__main__":
-    make(sys.argv[1] if len(sys.argv) > 1 else "M13", int(sys.argv[2]) if len(sys.argv) > 2 else 200000)
+    dts = tuple(float(v) for v in sys.argv[3].split(",")) if len(sys.argv) > 3 else (configs.DT_SMALL, configs.DT_LARGE)
+    make(sys.argv[1] if len(sys.argv) > 1 else "M13", int(sys.argv[2]) if len(sys.argv) > 2 else 200000, dts)

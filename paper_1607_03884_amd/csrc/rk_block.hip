@@ -17,10 +17,21 @@
 // its neighbours: coalesced); it forms E1/E2 and gives the FP64 residuals of
 // the refinement step that follows every FP32 solve.
 //
-// A state whose Newton iteration diverges twice in a row after its first
-// accepted step switches to refinement to convergence (three refinement
-// sweeps per solve) for the rest of the call: FP32 factors with FP64
-// residuals then give FP64-accurate solutions wherever cond(E) * 2^-24 < 1.
+// Every solve is refined against the FP64 matrices until the last
+// correction is below 1e-8 in the error weights (one to four sweeps); a
+// correction larger than the one before it ends the sweeps unapplied (the
+// iterate is then at the FP64 rounding floor, or cond(E) * 2^-24 >= 1 and
+// further sweeps would amplify the error).  A state whose Newton iteration
+// diverges twice in a row after its first accepted step switches to at least
+// three (at most six) sweeps per solve for the rest of the call.
+//
+// The FP32 factors are least accurate along the linear invariants: the
+// element (and total-mass) weights w satisfy w^T J = 0, so w^T E = (g/h) w^T
+// and E's smallest singular values, near g/h, lie in those directions, while
+// the largest follow ||J||; cond(E) grows like h ||J|| / g.  Where
+// cond(E) * 2^-24 approaches 1 the sweeps contract slowly and the sum of the
+// mass fractions keeps the error of the last Newton solve, a fraction of the
+// last increment (the exact solve would conserve it to rounding).
 //
 // Work distribution: a persistent grid whose blocks pull states from a device
 // queue, optionally in a caller-supplied order.
@@ -854,7 +865,12 @@ __global__ __launch_bounds__(BT) void radau_block_kernel(DevMech m, RadauParams 
             double W1 = rp.Ti[0] * Z1 + rp.Ti[1] * Z2 + rp.Ti[2] * Z3;
             double W2 = rp.Ti[3] * Z1 + rp.Ti[4] * Z2 + rp.Ti[5] * Z3;
             double W3 = rp.Ti[6] * Z1 + rp.Ti[7] * Z2 + rp.Ti[8] * Z3;
-            const int nref = fb ? 3 : 1;
+            // refinement sweeps per solve: at least nref, then more while the last
+            // correction is above 1e-8 in the error weights (an ill-conditioned
+            // iteration matrix needs more than one sweep for an FP64-accurate
+            // solve), at most nref_max
+            const int nref = fb ? 3 : 1, nref_max = fb ? 6 : 4;
+            const double sci = comp ? 1.0 / scw() : 0.0;
 
             eta = pow(fmax(eta, kU), 0.8);
             bool converged = false, diverged = false;
@@ -880,7 +896,8 @@ __global__ __launch_bounds__(BT) void radau_block_kernel(DevMech m, RadauParams 
                 const double b3 = comp ? G3 - (bh * W2 + ah * W3) : 0.0;
                 double dW1 = b1, dW2 = b2, dW3 = b3;
                 bsolve<CW>(F, L, part, row, active, N, true, dW1, dW2, dW3);
-                for (int rf = 0; rf < nref; ++rf) {
+                double cn_prev = 1e300;
+                for (int rf = 0; rf < nref_max; ++rf) {
                     // refinement against the FP64 matrices
                     double j1 = dW1, j2 = dW2, j3 = dW3;
                     bjv3<CW>(L, JS, LDJ, part, row, active, N, 3, j1, j2, j3);
@@ -888,9 +905,14 @@ __global__ __launch_bounds__(BT) void radau_block_kernel(DevMech m, RadauParams 
                     double q2 = comp ? b2 - ((ah * dW2 - j2) - bh * dW3) : 0.0;
                     double q3 = comp ? b3 - ((ah * dW3 - j3) + bh * dW2) : 0.0;
                     bsolve<CW>(F, L, part, row, active, N, true, q1, q2, q3);
+                    double cn = ((q1 * sci) * (q1 * sci) + (q2 * sci) * (q2 * sci)) + (q3 * sci) * (q3 * sci), zc = 0.0;
+                    bsum2(cn, zc, L.red, ph);
+                    if (!(cn < cn_prev)) break;
                     dW1 += q1;
                     dW2 += q2;
                     dW3 += q3;
+                    if (rf + 1 >= nref && sqrt(cn / (3 * N)) <= 1e-8) break;
+                    cn_prev = cn;
                 }
                 const double dZ1 = rp.T[0] * dW1 + rp.T[1] * dW2 + rp.T[2] * dW3;
                 const double dZ2 = rp.T[3] * dW1 + rp.T[4] * dW2 + rp.T[5] * dW3;
@@ -932,13 +954,19 @@ __global__ __launch_bounds__(BT) void radau_block_kernel(DevMech m, RadauParams 
                 double v = comp ? L.f0s[t] + dz : 0.0;
                 double ev = v, u2 = 0.0, u3 = 0.0;
                 bsolve<CW>(F, L, part, row, active, N, false, ev, u2, u3);
-                for (int rf = 0; rf < nref; ++rf) {
+                double cn_prev = 1e300;
+                for (int rf = 0; rf < nref_max; ++rf) {
                     double j1 = ev, j2 = 0.0, j3 = 0.0;
                     bjv3<CW>(L, JS, LDJ, part, row, active, N, 1, j1, j2, j3);
                     double q1 = comp ? v - (gh * ev - j1) : 0.0;
                     u2 = u3 = 0.0;
                     bsolve<CW>(F, L, part, row, active, N, false, q1, u2, u3);
+                    double cn = (q1 * sci) * (q1 * sci), zc = 0.0;
+                    bsum2(cn, zc, L.red, ph);
+                    if (!(cn < cn_prev)) break;
                     ev += q1;
+                    if (rf + 1 >= nref && sqrt(cn / N) <= 1e-8) break;
+                    cn_prev = cn;
                 }
                 double e2 = comp ? (ev / sc2) * (ev / sc2) : 0.0, zero = 0.0;
                 bsum2(e2, zero, L.red, ph);
@@ -950,13 +978,19 @@ __global__ __launch_bounds__(BT) void radau_block_kernel(DevMech m, RadauParams 
                     ev = v;
                     u2 = u3 = 0.0;
                     bsolve<CW>(F, L, part, row, active, N, false, ev, u2, u3);
-                    for (int rf = 0; rf < nref; ++rf) {
+                    double cn_prev = 1e300;
+                    for (int rf = 0; rf < nref_max; ++rf) {
                         double j1 = ev, j2 = 0.0, j3 = 0.0;
                         bjv3<CW>(L, JS, LDJ, part, row, active, N, 1, j1, j2, j3);
                         double q1 = comp ? v - (gh * ev - j1) : 0.0;
                         u2 = u3 = 0.0;
                         bsolve<CW>(F, L, part, row, active, N, false, q1, u2, u3);
+                        double cn = (q1 * sci) * (q1 * sci), zc = 0.0;
+                        bsum2(cn, zc, L.red, ph);
+                        if (!(cn < cn_prev)) break;
                         ev += q1;
+                        if (rf + 1 >= nref && sqrt(cn / N) <= 1e-8) break;
+                        cn_prev = cn;
                     }
                     e2 = comp ? (ev / sc2) * (ev / sc2) : 0.0;
                     zero = 0.0;

@@ -114,17 +114,20 @@ def train(mech: str, dt: float, data: Dict[str, np.ndarray], hidden=(128, 128), 
 
 
 if __name__ == "__main__":
-    # python -m paper_1607_03884_amd.predictor <mech> [output directory]
+    # python -m paper_1607_03884_amd.predictor <mech> [output directory] [dt,...] [hidden widths]
+    # e.g. "M53", or "M150 paper_1607_03884_amd/data 1e-4 256,256" (the 150-species file)
     import json
     import sys
     mech = sys.argv[1] if len(sys.argv) > 1 else "M13"
     outdir = sys.argv[2] if len(sys.argv) > 2 else configs.DATA_DIR
+    dts = tuple(float(v) for v in sys.argv[3].split(",")) if len(sys.argv) > 3 else (configs.DT_SMALL, configs.DT_LARGE)
+    hidden = tuple(int(v) for v in sys.argv[4].split(",")) if len(sys.argv) > 4 else (128, 128)
     os.makedirs(outdir, exist_ok=True)
-    for dt in (configs.DT_SMALL, configs.DT_LARGE):
+    for dt in dts:
         src = os.path.join(configs.DATA_DIR, f"{mech}_train_dt{dt:g}.npz")
         d = dict(np.load(src, allow_pickle=False))
         out = os.path.join(outdir, os.path.basename(path_for(mech, dt)))
-        rep = train(mech, dt, d, out_path=out, log=lambda s: print(s, flush=True))
+        rep = train(mech, dt, d, hidden=hidden, out_path=out, log=lambda s: print(s, flush=True))
         with open(out + ".json", "w") as fh:
             json.dump(rep, fh, indent=1)
         print(f"{mech} dt={dt:g}: wrote {out}", flush=True)
