@@ -226,6 +226,32 @@ int upload(rk_mech *m, const std::vector<Rx> &rx, const std::vector<double> &alo
     }
     m->sp_off[K] = (int)m->sp_rx.size();
     if (m->sp_rx.empty()) m->sp_rx.push_back(int2{0, 0});
+    // species -> reactions with a mass-action slot or a non-default efficiency
+    // of that species (the Jacobian's concentration columns)
+    m->jl_off.assign(K + 1, 0);
+    m->jl_rx.clear();
+    m->jl_em1.clear();
+    for (int k = 0; k < K; ++k) {
+        m->jl_off[k] = (int)m->jl_rx.size();
+        for (int j = 0; j < R; ++j) {
+            const Rx &x = rx[j];
+            int e = (x.r[0] == k) | (x.nr > 1 && x.r[1] == k) << 1 | (x.p[0] == k) << 2 | (x.np > 1 && x.p[1] == k) << 3;
+            double em1 = 0.0;
+            if (x.kind != 0 && x.eff[k] != 1.0) {
+                e |= 16;
+                em1 = x.eff[k] - 1.0;
+            }
+            if (e != 0) {
+                m->jl_rx.push_back(j << 5 | e);
+                m->jl_em1.push_back(em1);
+            }
+        }
+    }
+    m->jl_off[K] = (int)m->jl_rx.size();
+    if (m->jl_rx.empty()) {
+        m->jl_rx.push_back(0);
+        m->jl_em1.push_back(0.0);
+    }
     std::vector<double> invW(K);
     for (int k = 0; k < K; ++k) invW[k] = 1.0 / m->W[k];
 
@@ -237,7 +263,9 @@ int upload(rk_mech *m, const std::vector<Rx> &rx, const std::vector<double> &alo
         {m->rsp.data(), std::max(R, 1) * sizeof(int4), 0}, {m->rinfo.data(), std::max(R, 1) * sizeof(int), 0},
         {m->rpar.data(), std::max<size_t>(m->rpar.size(), 1) * sizeof(double), 0},
         {m->eff.data(), m->eff.size() * sizeof(double), 0},
-        {m->sp_off.data(), m->sp_off.size() * sizeof(int), 0}, {m->sp_rx.data(), m->sp_rx.size() * sizeof(int2), 0}};
+        {m->sp_off.data(), m->sp_off.size() * sizeof(int), 0}, {m->sp_rx.data(), m->sp_rx.size() * sizeof(int2), 0},
+        {m->jl_off.data(), m->jl_off.size() * sizeof(int), 0}, {m->jl_rx.data(), m->jl_rx.size() * sizeof(int), 0},
+        {m->jl_em1.data(), m->jl_em1.size() * sizeof(double), 0}};
     size_t total = 0;
     for (Part &p : parts) { p.off = total; total += (p.bytes + 255) / 256 * 256; }
     std::vector<char> host(total, 0);
@@ -262,6 +290,9 @@ int upload(rk_mech *m, const std::vector<Rx> &rx, const std::vector<double> &alo
     d.eff = reinterpret_cast<const double *>(b + parts[7].off);
     d.sp_off = reinterpret_cast<const int *>(b + parts[8].off);
     d.sp_rx = reinterpret_cast<const int2 *>(b + parts[9].off);
+    d.jl_off = reinterpret_cast<const int *>(b + parts[10].off);
+    d.jl_rx = reinterpret_cast<const int *>(b + parts[11].off);
+    d.jl_em1 = reinterpret_cast<const double *>(b + parts[12].off);
     e = hipEventCreate(&m->ev0);
     if (e == hipSuccess) e = hipEventCreate(&m->ev1);
     if (e != hipSuccess) return hip_fail(e, "hipEventCreate");

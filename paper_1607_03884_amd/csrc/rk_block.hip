@@ -301,6 +301,8 @@ __device__ __forceinline__ void jac_b(const DevMech &m, const BL &L, int t, doub
     double wdot = 0.0, dwdT = 0.0, sS = 0.0, ck = 0.0;
     int i = x.isY ? m.sp_off[x.k] : 0;
     const int iend = x.isY ? m.sp_off[x.k + 1] : 0;
+    int jp = x.isY ? m.jl_off[x.k] : 0;
+    const int jpend = x.isY ? m.jl_off[x.k + 1] : 0;
     double *rec = L.q;
     for (int j0 = 0; j0 < R; j0 += BCH) {
         const int j1 = min(R, j0 + BCH);
@@ -324,25 +326,20 @@ __device__ __forceinline__ void jac_b(const DevMech &m, const BL &L, int t, doub
             rc[7] = -sMA * e.kr * Cp0;
         }
         __syncthreads();
+        // column m (lane m + 1): the reactions of this chunk in species m's
+        // list, in reaction order (reactions outside the list contribute 0)
         if (x.isY) {
-            const int mm = x.k;
-            typedef const __attribute__((address_space(4))) int cint;
-            cint *rspc = (cint *)m.rsp;
-            cint *rinfoc = (cint *)m.rinfo;
-            for (int j = j0; j < j1; ++j) {
-                int4 sp;
-                sp.x = rspc[4 * j];
-                sp.y = rspc[4 * j + 1];
-                sp.z = rspc[4 * j + 2];
-                sp.w = rspc[4 * j + 3];
-                const int info = rinfoc[j];
+            for (; jp < jpend; ++jp) {
+                const int e = m.jl_rx[jp], j = e >> 5;
+                if (j >= j1) break;
+                const int4 sp = m.rsp[j];
                 const double *rc = rec + 8 * (j - j0);
                 double dq = 0.0;
-                if (mm == sp.x) dq += rc[4];
-                if (mm == sp.y) dq += rc[5];
-                if (mm == sp.z) dq += rc[6];
-                if (mm == sp.w) dq += rc[7];
-                if (info & 15) dq += rc[3] * (m.eff[(size_t)((info >> 12) - 1) * K + mm] - 1.0);
+                if (e & 1) dq += rc[4];
+                if (e & 2) dq += rc[5];
+                if (e & 4) dq += rc[6];
+                if (e & 8) dq += rc[7];
+                if (e & 16) dq += rc[3] * m.jl_em1[jp];
                 if (dq != 0.0) {
                     unsafeAtomicAdd(col + 1 + sp.x, -dq);
                     if (sp.y >= 0) unsafeAtomicAdd(col + 1 + sp.y, -dq);
@@ -894,17 +891,27 @@ __global__ __launch_bounds__(BT) void radau_block_kernel(DevMech m, RadauParams 
                 const double b1 = comp ? G1 - gh * W1 : 0.0;
                 const double b2 = comp ? G2 - (ah * W2 - bh * W3) : 0.0;
                 const double b3 = comp ? G3 - (bh * W2 + ah * W3) : 0.0;
-                double dW1 = b1, dW2 = b2, dW3 = b3;
-                bsolve<CW>(F, L, part, row, active, N, true, dW1, dW2, dW3);
-                double cn_prev = 1e300;
-                for (int rf = 0; rf < nref_max; ++rf) {
-                    // refinement against the FP64 matrices
-                    double j1 = dW1, j2 = dW2, j3 = dW3;
-                    bjv3<CW>(L, JS, LDJ, part, row, active, N, 3, j1, j2, j3);
-                    double q1 = comp ? b1 - (gh * dW1 - j1) : 0.0;
-                    double q2 = comp ? b2 - ((ah * dW2 - j2) - bh * dW3) : 0.0;
-                    double q3 = comp ? b3 - ((ah * dW3 - j3) + bh * dW2) : 0.0;
+                // the solve and its refinement sweeps share one substitution
+                // site (rf = -1: the plain solve)
+                double dW1 = 0.0, dW2 = 0.0, dW3 = 0.0, cn_prev = 1e300;
+#pragma nounroll
+                for (int rf = -1; rf < nref_max; ++rf) {
+                    double q1 = b1, q2 = b2, q3 = b3;
+                    if (rf >= 0) {
+                        // refinement against the FP64 matrices
+                        double j1 = dW1, j2 = dW2, j3 = dW3;
+                        bjv3<CW>(L, JS, LDJ, part, row, active, N, 3, j1, j2, j3);
+                        q1 = comp ? b1 - (gh * dW1 - j1) : 0.0;
+                        q2 = comp ? b2 - ((ah * dW2 - j2) - bh * dW3) : 0.0;
+                        q3 = comp ? b3 - ((ah * dW3 - j3) + bh * dW2) : 0.0;
+                    }
                     bsolve<CW>(F, L, part, row, active, N, true, q1, q2, q3);
+                    if (rf < 0) {
+                        dW1 = q1;
+                        dW2 = q2;
+                        dW3 = q3;
+                        continue;
+                    }
                     double cn = ((q1 * sci) * (q1 * sci) + (q2 * sci) * (q2 * sci)) + (q3 * sci) * (q3 * sci), zc = 0.0;
                     bsum2(cn, zc, L.red, ph);
                     if (!(cn < cn_prev)) break;
@@ -952,39 +959,30 @@ __global__ __launch_bounds__(BT) void radau_block_kernel(DevMech m, RadauParams 
                 const double dz = (rp.d[0] * Z1 + rp.d[1] * Z2 + rp.d[2] * Z3) * invh;
                 const double sc2 = comp ? atol + rtol * fmax(fabs(y), fabs(y + Z3)) : 1.0;
                 double v = comp ? L.f0s[t] + dz : 0.0;
-                double ev = v, u2 = 0.0, u3 = 0.0;
-                bsolve<CW>(F, L, part, row, active, N, false, ev, u2, u3);
-                double cn_prev = 1e300;
-                for (int rf = 0; rf < nref_max; ++rf) {
-                    double j1 = ev, j2 = 0.0, j3 = 0.0;
-                    bjv3<CW>(L, JS, LDJ, part, row, active, N, 1, j1, j2, j3);
-                    double q1 = comp ? v - (gh * ev - j1) : 0.0;
-                    u2 = u3 = 0.0;
-                    bsolve<CW>(F, L, part, row, active, N, false, q1, u2, u3);
-                    double cn = (q1 * sci) * (q1 * sci), zc = 0.0;
-                    bsum2(cn, zc, L.red, ph);
-                    if (!(cn < cn_prev)) break;
-                    ev += q1;
-                    if (rf + 1 >= nref && sqrt(cn / N) <= 1e-8) break;
-                    cn_prev = cn;
-                }
-                double e2 = comp ? (ev / sc2) * (ev / sc2) : 0.0, zero = 0.0;
-                bsum2(e2, zero, L.red, ph);
-                double err = fmax(sqrt(e2 / N), 1e-10);
-                if (err >= 1.0 && (first || reject)) {
-                    const double fe = rhs_b(m, L, t, y + ev, P, ph);
-                    bump(K_NFEV, 1);
-                    v = comp ? fe + dz : 0.0;
-                    ev = v;
-                    u2 = u3 = 0.0;
-                    bsolve<CW>(F, L, part, row, active, N, false, ev, u2, u3);
+                double ev = 0.0, err = 1.0;
+                // at most two attempts (the second with f(y0 + err) on a first
+                // or post-rejection step); one solve-and-refine site for both
+#pragma nounroll
+                for (int att = 0; att < 2; ++att) {
+                    if (att == 1) {
+                        const double fe = rhs_b(m, L, t, y + ev, P, ph);
+                        bump(K_NFEV, 1);
+                        v = comp ? fe + dz : 0.0;
+                    }
                     double cn_prev = 1e300;
-                    for (int rf = 0; rf < nref_max; ++rf) {
-                        double j1 = ev, j2 = 0.0, j3 = 0.0;
-                        bjv3<CW>(L, JS, LDJ, part, row, active, N, 1, j1, j2, j3);
-                        double q1 = comp ? v - (gh * ev - j1) : 0.0;
-                        u2 = u3 = 0.0;
+#pragma nounroll
+                    for (int rf = -1; rf < nref_max; ++rf) {
+                        double q1 = v, u2 = 0.0, u3 = 0.0;
+                        if (rf >= 0) {
+                            double j1 = ev, j2 = 0.0, j3 = 0.0;
+                            bjv3<CW>(L, JS, LDJ, part, row, active, N, 1, j1, j2, j3);
+                            q1 = comp ? v - (gh * ev - j1) : 0.0;
+                        }
                         bsolve<CW>(F, L, part, row, active, N, false, q1, u2, u3);
+                        if (rf < 0) {
+                            ev = q1;
+                            continue;
+                        }
                         double cn = (q1 * sci) * (q1 * sci), zc = 0.0;
                         bsum2(cn, zc, L.red, ph);
                         if (!(cn < cn_prev)) break;
@@ -992,10 +990,10 @@ __global__ __launch_bounds__(BT) void radau_block_kernel(DevMech m, RadauParams 
                         if (rf + 1 >= nref && sqrt(cn / N) <= 1e-8) break;
                         cn_prev = cn;
                     }
-                    e2 = comp ? (ev / sc2) * (ev / sc2) : 0.0;
-                    zero = 0.0;
+                    double e2 = comp ? (ev / sc2) * (ev / sc2) : 0.0, zero = 0.0;
                     bsum2(e2, zero, L.red, ph);
                     err = fmax(sqrt(e2 / N), 1e-10);
+                    if (att == 1 || !(err >= 1.0 && (first || reject))) break;
                 }
                 if (!isfinite(err)) err = 1e300;
 

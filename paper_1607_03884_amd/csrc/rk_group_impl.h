@@ -359,9 +359,11 @@ __device__ __forceinline__ void jac_g(const DevMech &m, const GL &L, int r, doub
     const Mix x = mixture<G>(m, L, r, yv, P, th);
     const double T = x.T, invT = x.invT, rho = x.rho, Wbar = x.Wbar;
     for (int i = r; i < NC * LD; i += G) L.J[i] = 0.0;
-    double wdot = 0.0, dwdT = 0.0, sS = 0.0;
+    double wdot = 0.0, dwdT = 0.0, sS = 0.0, ck = 0.0;
     int i = x.isY ? L.spoff[x.k] : 0;
     const int iend = x.isY ? L.spoff[x.k + 1] : 0;
+    int jp = x.isY ? m.jl_off[x.k] : 0;
+    const int jpend = x.isY ? m.jl_off[x.k + 1] : 0;
     for (int j0 = 0; j0 < R; j0 += CH) {
         const int j1 = min(R, j0 + CH);
         // per-reaction records: q, dq/dT|C, S, dense coefficient, 4 mass-action partials
@@ -385,30 +387,22 @@ __device__ __forceinline__ void jac_g(const DevMech &m, const GL &L, int r, doub
             rc[7] = -sMA * e.kr * Cp0;
         }
         sync_wave();
-        // Mkm = sum_j nu_kj dq_j/dC_m into the Y block; lane r owns column r (species r-1)
+        // Mkm = sum_j nu_kj dq_j/dC_m into the Y block; lane r owns column r
+        // (species r-1) and walks the reactions of this chunk in its species'
+        // list (mass-action slots and non-default efficiencies); the common
+        // third-body part sum_j nu_kj ctb_j of row k is added with the row pass
         if (x.isY) {
-            const int mm = x.k;
-            // the reaction tables are read-only and indexed uniformly here: read
-            // them through the constant address space so the loads go to the
-            // scalar cache (through a generic pointer they become vector loads,
-            // since the kernel also writes global memory)
-            typedef const __attribute__((address_space(4))) int cint;
-            cint *rspc = (cint *)m.rsp;       // 4 ints per reaction
-            cint *rinfoc = (cint *)m.rinfo;
-            for (int j = j0; j < j1; ++j) {
-                int4 sp;
-                sp.x = rspc[4 * j];
-                sp.y = rspc[4 * j + 1];
-                sp.z = rspc[4 * j + 2];
-                sp.w = rspc[4 * j + 3];
-                const int info = rinfoc[j];
+            for (; jp < jpend; ++jp) {
+                const int e = m.jl_rx[jp], j = e >> 5;
+                if (j >= j1) break;
+                const int4 sp = m.rsp[j];
                 const double *rc = L.rec + 8 * (j - j0);
                 double dq = 0.0;
-                if (mm == sp.x) dq += rc[4];
-                if (mm == sp.y) dq += rc[5];
-                if (mm == sp.z) dq += rc[6];
-                if (mm == sp.w) dq += rc[7];
-                if (info & 15) dq += rc[3] * L.eff[(size_t)((info >> 12) - 1) * K + mm];
+                if (e & 1) dq += rc[4];
+                if (e & 2) dq += rc[5];
+                if (e & 4) dq += rc[6];
+                if (e & 8) dq += rc[7];
+                if (e & 16) dq += rc[3] * m.jl_em1[jp];
                 if (dq != 0.0) {
                     L.J[(1 + sp.x) * LD + r] -= dq;
                     if (sp.y >= 0) L.J[(1 + sp.y) * LD + r] -= dq;
@@ -425,6 +419,7 @@ __device__ __forceinline__ void jac_g(const DevMech &m, const GL &L, int r, doub
             wdot += nu * rc[0];
             dwdT += nu * rc[1];
             sS += nu * rc[2];
+            ck += nu * rc[3];       // third-body coefficient (0 for elementary reactions)
         }
         sync_wave();
     }
@@ -435,11 +430,13 @@ __device__ __forceinline__ void jac_g(const DevMech &m, const GL &L, int r, doub
     const double hw = gsum<G>(x.isY ? hk * wdot : 0.0);
     const double dHdT = gsum<G>(x.isY ? th.cp * wdot + hk * (dwdT - sS * invT) : 0.0);
     const double hsS = gsum<G>(x.isY ? hk * sS : 0.0);
+    const double hck = gsum<G>(x.isY ? hk * ck : 0.0);
     const double rcp = rho * cpmix;
     const double fT = -hw / rcp;
     if (x.isY) {
         double hM = 0.0;
         for (int k = 0; k < K; ++k) hM += L.h[k] * T * L.J[(1 + k) * LD + r];
+        hM += hck;      // the rows' third-body constants, summed with the enthalpies
         const double dHdY = (rho * hM - Wbar * hsS) * x.invW;
         L.J[r] = -dHdY / rcp - fT * (th.cp * x.invW / cpmix - Wbar * x.invW);
     }
@@ -453,7 +450,7 @@ __device__ __forceinline__ void jac_g(const DevMech &m, const GL &L, int r, doub
         double *row = L.J + r * LD;
         row[0] = Wk / rho * (dwdT - sS * invT) + fk * invT;
         const __attribute__((address_space(4))) double *iw = (const __attribute__((address_space(4))) double *)m.invW;
-        for (int c = 1; c <= K; ++c) row[c] = (Wk * row[c] + a) * iw[c - 1];
+        for (int c = 1; c <= K; ++c) row[c] = (Wk * (row[c] + ck) + a) * iw[c - 1];
     }
     sync_wave();
 }

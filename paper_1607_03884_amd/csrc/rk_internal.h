@@ -33,6 +33,12 @@ struct DevMech {
     const double *eff;     // [n3b][K] collision efficiencies
     const int *sp_off;     // [K+1] species -> reaction list offsets
     const int2 *sp_rx;     // [sp_off[K]] (reaction, net stoichiometric coefficient)
+    // species m -> the reactions whose rate depends on C_m other than through
+    // the mixture total of a third body: m fills a reactant or product slot,
+    // or m has a non-default collision efficiency (reaction order)
+    const int *jl_off;     // [K+1]
+    const int *jl_rx;      // reaction << 5 | slots holding m (bits 0-3: r0, r1, p0, p1) | 16 if efficiency != 1
+    const double *jl_em1;  // efficiency - 1 of m in that reaction (0 unless bit 4)
 };
 
 // Radau IIA constants and integrator parameters (computed on the host).
@@ -183,6 +189,8 @@ struct rk_mech {
     std::vector<int4> rsp;
     std::vector<int> sp_off;
     std::vector<int2> sp_rx;
+    std::vector<int> jl_off, jl_rx;
+    std::vector<double> jl_em1;
     // device
     rk::DevMech dev{};
     void *dev_block = nullptr;
