@@ -248,6 +248,25 @@ int upload(rk_mech *m, const std::vector<Rx> &rx, const std::vector<double> &alo
         }
     }
     m->jl_off[K] = (int)m->jl_rx.size();
+    // third-body rows: species with a non-default efficiency
+    m->tb_off.assign(m->n3b + 1, 0);
+    m->tb_sp.clear();
+    m->tb_em1.clear();
+    for (int b = 0; b < m->n3b; ++b) {
+        m->tb_off[b] = (int)m->tb_sp.size();
+        for (int k = 0; k < K; ++k) {
+            const double ef = m->eff[(size_t)b * K + k];
+            if (ef != 1.0) {
+                m->tb_sp.push_back(k);
+                m->tb_em1.push_back(ef - 1.0);
+            }
+        }
+    }
+    m->tb_off[m->n3b] = (int)m->tb_sp.size();
+    if (m->tb_sp.empty()) {
+        m->tb_sp.push_back(0);
+        m->tb_em1.push_back(0.0);
+    }
     if (m->jl_rx.empty()) {
         m->jl_rx.push_back(0);
         m->jl_em1.push_back(0.0);
@@ -265,7 +284,9 @@ int upload(rk_mech *m, const std::vector<Rx> &rx, const std::vector<double> &alo
         {m->eff.data(), m->eff.size() * sizeof(double), 0},
         {m->sp_off.data(), m->sp_off.size() * sizeof(int), 0}, {m->sp_rx.data(), m->sp_rx.size() * sizeof(int2), 0},
         {m->jl_off.data(), m->jl_off.size() * sizeof(int), 0}, {m->jl_rx.data(), m->jl_rx.size() * sizeof(int), 0},
-        {m->jl_em1.data(), m->jl_em1.size() * sizeof(double), 0}};
+        {m->jl_em1.data(), m->jl_em1.size() * sizeof(double), 0},
+        {m->tb_off.data(), m->tb_off.size() * sizeof(int), 0}, {m->tb_sp.data(), m->tb_sp.size() * sizeof(int), 0},
+        {m->tb_em1.data(), m->tb_em1.size() * sizeof(double), 0}};
     size_t total = 0;
     for (Part &p : parts) { p.off = total; total += (p.bytes + 255) / 256 * 256; }
     std::vector<char> host(total, 0);
@@ -293,6 +314,9 @@ int upload(rk_mech *m, const std::vector<Rx> &rx, const std::vector<double> &alo
     d.jl_off = reinterpret_cast<const int *>(b + parts[10].off);
     d.jl_rx = reinterpret_cast<const int *>(b + parts[11].off);
     d.jl_em1 = reinterpret_cast<const double *>(b + parts[12].off);
+    d.tb_off = reinterpret_cast<const int *>(b + parts[13].off);
+    d.tb_sp = reinterpret_cast<const int *>(b + parts[14].off);
+    d.tb_em1 = reinterpret_cast<const double *>(b + parts[15].off);
     e = hipEventCreate(&m->ev0);
     if (e == hipSuccess) e = hipEventCreate(&m->ev1);
     if (e != hipSuccess) return hip_fail(e, "hipEventCreate");

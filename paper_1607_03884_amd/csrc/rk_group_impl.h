@@ -119,7 +119,8 @@ struct GL {
     int *ctr;         // rarely read per-state counters (lane 0 updates them)
     // mechanism tables read inside loops, staged in block-shared LDS: the
     // species -> reaction lists (entry = reaction << 4 | (nu + 8)) always,
-    // the collision efficiencies for 16-lane groups (global memory otherwise)
+    // the dense collision efficiencies for 16-lane groups (null otherwise:
+    // the wavefront groups use the sparse rows in global memory)
     const int *spoff;
     const int *sprx;
     const double *eff;
@@ -195,7 +196,7 @@ __device__ __forceinline__ void stage_tables(const DevMech &m, double *smem, GL 
         for (int i = threadIdx.x; i < m.n3b * K; i += kWave) se[i] = m.eff[i];
         L.eff = se;
     } else {
-        L.eff = m.eff;
+        L.eff = nullptr;
     }
     sync_wave();
 }
@@ -224,7 +225,7 @@ struct RxEval {
 };
 
 __device__ __forceinline__ RxEval eval_reaction(const DevMech &m, const GL &L, int j, double T, double lnT, double invT,
-                                                double lnPRT, bool derivs) {
+                                                double lnPRT, double ctot, bool derivs) {
     RxEval e;
     e.sp = m.rsp[j];
     const int info = m.rinfo[j];
@@ -232,14 +233,22 @@ __device__ __forceinline__ RxEval eval_reaction(const DevMech &m, const GL &L, i
     e.kind = info & 15;
     e.nr = (info >> 4) & 15;
     e.np = (info >> 8) & 15;
-    const int K = m.K;
     double kf = p[P_A] * exp(p[P_B] * lnT - p[P_EAR] * invT);
     double dlnkf = (p[P_B] + p[P_EAR] * invT) * invT;
     double Mc = 0.0, dlnkf_dM = 0.0;
     if (e.kind != 0) {
-        const double *ef = L.eff + (size_t)((info >> 12) - 1) * K;
+        const int b = (info >> 12) - 1;
+        if (L.eff) {
+            // 16-lane groups: the dense row staged in LDS
+            const double *ef = L.eff + (size_t)b * m.K;
 #pragma unroll 4
-        for (int k = 0; k < K; ++k) Mc += ef[k] * L.C[k];
+            for (int k = 0; k < m.K; ++k) Mc += ef[k] * L.C[k];
+        } else {
+            // [M] = sum_k eff_k C_k = sum_k C_k + sum over the non-default
+            // efficiencies of (eff_k - 1) C_k
+            Mc = ctot;
+            for (int p = m.tb_off[b]; p < m.tb_off[b + 1]; ++p) Mc += m.tb_em1[p] * L.C[m.tb_sp[p]];
+        }
     }
     if (e.kind == 2) {
         const double k0 = p[P_A0] * exp(p[P_B0] * lnT - p[P_EA0R] * invT);
@@ -287,7 +296,7 @@ __device__ __forceinline__ RxEval eval_reaction(const DevMech &m, const GL &L, i
 }
 
 struct Mix {
-    double T, Wbar, rho, invW, Y, lnT, invT, lnPRT;
+    double T, Wbar, rho, invW, Y, lnT, invT, lnPRT, ctot;
     bool isY;
     int k;
 };
@@ -304,6 +313,7 @@ __device__ __forceinline__ Mix mixture(const DevMech &m, const GL &L, int r, dou
     const double sumYW = gsum<G>(x.Y * x.invW);
     x.Wbar = 1.0 / sumYW;
     x.rho = P * x.Wbar / (kRu * x.T);
+    x.ctot = x.rho * sumYW;       // total concentration sum_k C_k
     x.lnT = log(x.T);
     x.invT = 1.0 / x.T;
     x.lnPRT = log(kPatm / (kRu * x.T));
@@ -331,7 +341,7 @@ __device__ __forceinline__ double rhs_g(const DevMech &m, const GL &L, int r, do
     // one round overlap the arithmetic of the previous), then each species
     // lane sums its list in reaction order
     for (int j = r; j < R; j += G) {
-        const RxEval e = eval_reaction(m, L, j, x.T, x.lnT, x.invT, x.lnPRT, false);
+        const RxEval e = eval_reaction(m, L, j, x.T, x.lnT, x.invT, x.lnPRT, x.ctot, false);
         double q = e.kf * e.Pf - e.kr * e.Pp;
         if (e.kind == 1) q *= e.Mc;
         L.q[j] = q;
@@ -368,7 +378,7 @@ __device__ __forceinline__ void jac_g(const DevMech &m, const GL &L, int r, doub
         const int j1 = min(R, j0 + CH);
         // per-reaction records: q, dq/dT|C, S, dense coefficient, 4 mass-action partials
         for (int j = j0 + r; j < j1; j += G) {
-            const RxEval e = eval_reaction(m, L, j, T, x.lnT, invT, x.lnPRT, true);
+            const RxEval e = eval_reaction(m, L, j, T, x.lnT, invT, x.lnPRT, x.ctot, true);
             const double Rj = e.kf * e.Pf - e.kr * e.Pp;
             const double dRdT = Rj * e.dlnkf + e.kr * e.Pp * e.dlnKc;
             const double sMA = e.kind == 1 ? e.Mc : 1.0;

@@ -39,6 +39,11 @@ struct DevMech {
     const int *jl_off;     // [K+1]
     const int *jl_rx;      // reaction << 5 | slots holding m (bits 0-3: r0, r1, p0, p1) | 16 if efficiency != 1
     const double *jl_em1;  // efficiency - 1 of m in that reaction (0 unless bit 4)
+    // third-body row b -> the species with a non-default efficiency:
+    // [M]_b = sum_k C_k + sum over the list of (efficiency - 1) C_k
+    const int *tb_off;     // [n3b+1]
+    const int *tb_sp;      // species
+    const double *tb_em1;  // efficiency - 1
 };
 
 // Radau IIA constants and integrator parameters (computed on the host).
@@ -189,8 +194,8 @@ struct rk_mech {
     std::vector<int4> rsp;
     std::vector<int> sp_off;
     std::vector<int2> sp_rx;
-    std::vector<int> jl_off, jl_rx;
-    std::vector<double> jl_em1;
+    std::vector<int> jl_off, jl_rx, tb_off, tb_sp;
+    std::vector<double> jl_em1, tb_em1;
     // device
     rk::DevMech dev{};
     void *dev_block = nullptr;
