@@ -229,10 +229,9 @@ int upload(rk_mech *m, const std::vector<Rx> &rx, const std::vector<double> &alo
     // species -> reactions with a mass-action slot or a non-default efficiency
     // of that species (the Jacobian's concentration columns)
     m->jl_off.assign(K + 1, 0);
-    m->jl_rx.clear();
-    m->jl_em1.clear();
+    m->jl.clear();
     for (int k = 0; k < K; ++k) {
-        m->jl_off[k] = (int)m->jl_rx.size();
+        m->jl_off[k] = (int)m->jl.size();
         for (int j = 0; j < R; ++j) {
             const Rx &x = rx[j];
             int e = (x.r[0] == k) | (x.nr > 1 && x.r[1] == k) << 1 | (x.p[0] == k) << 2 | (x.np > 1 && x.p[1] == k) << 3;
@@ -241,36 +240,23 @@ int upload(rk_mech *m, const std::vector<Rx> &rx, const std::vector<double> &alo
                 e |= 16;
                 em1 = x.eff[k] - 1.0;
             }
-            if (e != 0) {
-                m->jl_rx.push_back(j << 5 | e);
-                m->jl_em1.push_back(em1);
-            }
+            if (e != 0) m->jl.push_back(rk::JlEnt{em1, j << 5 | e, 0});
         }
     }
-    m->jl_off[K] = (int)m->jl_rx.size();
+    m->jl_off[K] = (int)m->jl.size();
+    if (m->jl.empty()) m->jl.push_back(rk::JlEnt{0.0, 0, 0});
     // third-body rows: species with a non-default efficiency
     m->tb_off.assign(m->n3b + 1, 0);
-    m->tb_sp.clear();
-    m->tb_em1.clear();
+    m->tb.clear();
     for (int b = 0; b < m->n3b; ++b) {
-        m->tb_off[b] = (int)m->tb_sp.size();
+        m->tb_off[b] = (int)m->tb.size();
         for (int k = 0; k < K; ++k) {
             const double ef = m->eff[(size_t)b * K + k];
-            if (ef != 1.0) {
-                m->tb_sp.push_back(k);
-                m->tb_em1.push_back(ef - 1.0);
-            }
+            if (ef != 1.0) m->tb.push_back(rk::TbEnt{ef - 1.0, k, 0});
         }
     }
-    m->tb_off[m->n3b] = (int)m->tb_sp.size();
-    if (m->tb_sp.empty()) {
-        m->tb_sp.push_back(0);
-        m->tb_em1.push_back(0.0);
-    }
-    if (m->jl_rx.empty()) {
-        m->jl_rx.push_back(0);
-        m->jl_em1.push_back(0.0);
-    }
+    m->tb_off[m->n3b] = (int)m->tb.size();
+    if (m->tb.empty()) m->tb.push_back(rk::TbEnt{0.0, 0, 0});
     std::vector<double> invW(K);
     for (int k = 0; k < K; ++k) invW[k] = 1.0 / m->W[k];
 
@@ -283,10 +269,8 @@ int upload(rk_mech *m, const std::vector<Rx> &rx, const std::vector<double> &alo
         {m->rpar.data(), std::max<size_t>(m->rpar.size(), 1) * sizeof(double), 0},
         {m->eff.data(), m->eff.size() * sizeof(double), 0},
         {m->sp_off.data(), m->sp_off.size() * sizeof(int), 0}, {m->sp_rx.data(), m->sp_rx.size() * sizeof(int2), 0},
-        {m->jl_off.data(), m->jl_off.size() * sizeof(int), 0}, {m->jl_rx.data(), m->jl_rx.size() * sizeof(int), 0},
-        {m->jl_em1.data(), m->jl_em1.size() * sizeof(double), 0},
-        {m->tb_off.data(), m->tb_off.size() * sizeof(int), 0}, {m->tb_sp.data(), m->tb_sp.size() * sizeof(int), 0},
-        {m->tb_em1.data(), m->tb_em1.size() * sizeof(double), 0}};
+        {m->jl_off.data(), m->jl_off.size() * sizeof(int), 0}, {m->jl.data(), m->jl.size() * sizeof(rk::JlEnt), 0},
+        {m->tb_off.data(), m->tb_off.size() * sizeof(int), 0}, {m->tb.data(), m->tb.size() * sizeof(rk::TbEnt), 0}};
     size_t total = 0;
     for (Part &p : parts) { p.off = total; total += (p.bytes + 255) / 256 * 256; }
     std::vector<char> host(total, 0);
@@ -312,11 +296,9 @@ int upload(rk_mech *m, const std::vector<Rx> &rx, const std::vector<double> &alo
     d.sp_off = reinterpret_cast<const int *>(b + parts[8].off);
     d.sp_rx = reinterpret_cast<const int2 *>(b + parts[9].off);
     d.jl_off = reinterpret_cast<const int *>(b + parts[10].off);
-    d.jl_rx = reinterpret_cast<const int *>(b + parts[11].off);
-    d.jl_em1 = reinterpret_cast<const double *>(b + parts[12].off);
-    d.tb_off = reinterpret_cast<const int *>(b + parts[13].off);
-    d.tb_sp = reinterpret_cast<const int *>(b + parts[14].off);
-    d.tb_em1 = reinterpret_cast<const double *>(b + parts[15].off);
+    d.jl = reinterpret_cast<const rk::JlEnt *>(b + parts[11].off);
+    d.tb_off = reinterpret_cast<const int *>(b + parts[12].off);
+    d.tb = reinterpret_cast<const rk::TbEnt *>(b + parts[13].off);
     e = hipEventCreate(&m->ev0);
     if (e == hipSuccess) e = hipEventCreate(&m->ev1);
     if (e != hipSuccess) return hip_fail(e, "hipEventCreate");

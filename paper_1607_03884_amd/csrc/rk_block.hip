@@ -329,22 +329,36 @@ __device__ __forceinline__ void jac_b(const DevMech &m, const BL &L, int t, doub
         // column m (lane m + 1): the reactions of this chunk in species m's
         // list, in reaction order (reactions outside the list contribute 0)
         if (x.isY) {
-            for (; jp < jpend; ++jp) {
-                const int e = m.jl_rx[jp], j = e >> 5;
-                if (j >= j1) break;
-                const int4 sp = m.rsp[j];
-                const double *rc = rec + 8 * (j - j0);
-                double dq = 0.0;
-                if (e & 1) dq += rc[4];
-                if (e & 2) dq += rc[5];
-                if (e & 4) dq += rc[6];
-                if (e & 8) dq += rc[7];
-                if (e & 16) dq += rc[3] * m.jl_em1[jp];
-                if (dq != 0.0) {
-                    unsafeAtomicAdd(col + 1 + sp.x, -dq);
-                    if (sp.y >= 0) unsafeAtomicAdd(col + 1 + sp.y, -dq);
-                    unsafeAtomicAdd(col + 1 + sp.z, dq);
-                    if (sp.w >= 0) unsafeAtomicAdd(col + 1 + sp.w, dq);
+            // entries fetched four at a time so their loads overlap
+            bool more = true;
+            while (more && jp < jpend) {
+                JlEnt en[4];
+                int4 spv[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) en[u] = jp + u < jpend ? m.jl[jp + u] : JlEnt{0.0, R << 5, 0};
+#pragma unroll
+                for (int u = 0; u < 4; ++u) spv[u] = (en[u].e >> 5) < j1 ? m.rsp[en[u].e >> 5] : int4{0, -1, 0, -1};
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int e = en[u].e, j = e >> 5;
+                    more = more && j < j1;
+                    if (more) {
+                        const int4 sp = spv[u];
+                        const double *rc = rec + 8 * (j - j0);
+                        double dq = 0.0;
+                        if (e & 1) dq += rc[4];
+                        if (e & 2) dq += rc[5];
+                        if (e & 4) dq += rc[6];
+                        if (e & 8) dq += rc[7];
+                        if (e & 16) dq += rc[3] * en[u].em1;
+                        if (dq != 0.0) {
+                            unsafeAtomicAdd(col + 1 + sp.x, -dq);
+                            if (sp.y >= 0) unsafeAtomicAdd(col + 1 + sp.y, -dq);
+                            unsafeAtomicAdd(col + 1 + sp.z, dq);
+                            if (sp.w >= 0) unsafeAtomicAdd(col + 1 + sp.w, dq);
+                        }
+                        ++jp;
+                    }
                 }
             }
         }

@@ -224,17 +224,30 @@ struct RxEval {
     int4 sp;
 };
 
-__device__ __forceinline__ RxEval eval_reaction(const DevMech &m, const GL &L, int j, double T, double lnT, double invT,
-                                                double lnPRT, double ctot, bool derivs) {
+// The table entries every reaction needs (slots, kind word, Arrhenius
+// parameters, sum of nu).
+struct RxHead {
+    int4 sp;
+    int info;
+    double A, B, EaR, dnu;
+};
+
+__device__ __forceinline__ RxHead rx_head(const DevMech &m, int j) {
+    const double *p = m.rpar + (size_t)j * P_NPAR;
+    return RxHead{m.rsp[j], m.rinfo[j], p[P_A], p[P_B], p[P_EAR], p[P_DNU]};
+}
+
+__device__ __forceinline__ RxEval eval_reaction(const DevMech &m, const GL &L, int j, const RxHead &hd, double T,
+                                                double lnT, double invT, double lnPRT, double ctot, bool derivs) {
     RxEval e;
-    e.sp = m.rsp[j];
-    const int info = m.rinfo[j];
+    e.sp = hd.sp;
+    const int info = hd.info;
     const double *p = m.rpar + (size_t)j * P_NPAR;
     e.kind = info & 15;
     e.nr = (info >> 4) & 15;
     e.np = (info >> 8) & 15;
-    double kf = p[P_A] * exp(p[P_B] * lnT - p[P_EAR] * invT);
-    double dlnkf = (p[P_B] + p[P_EAR] * invT) * invT;
+    double kf = hd.A * exp(hd.B * lnT - hd.EaR * invT);
+    double dlnkf = (hd.B + hd.EaR * invT) * invT;
     double Mc = 0.0, dlnkf_dM = 0.0;
     if (e.kind != 0) {
         const int b = (info >> 12) - 1;
@@ -246,8 +259,17 @@ __device__ __forceinline__ RxEval eval_reaction(const DevMech &m, const GL &L, i
         } else {
             // [M] = sum_k eff_k C_k = sum_k C_k + sum over the non-default
             // efficiencies of (eff_k - 1) C_k
+            // (entries fetched eight at a time so their loads overlap)
             Mc = ctot;
-            for (int p = m.tb_off[b]; p < m.tb_off[b + 1]; ++p) Mc += m.tb_em1[p] * L.C[m.tb_sp[p]];
+            const int p1 = m.tb_off[b + 1];
+            for (int p = m.tb_off[b]; p < p1; p += 8) {
+                TbEnt te[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) te[u] = p + u < p1 ? m.tb[p + u] : TbEnt{0.0, 0, 0};
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (p + u < p1) Mc += te[u].em1 * L.C[te[u].k];
+            }
         }
     }
     if (e.kind == 2) {
@@ -282,10 +304,10 @@ __device__ __forceinline__ RxEval eval_reaction(const DevMech &m, const GL &L, i
     double Pf = L.C[sp.x], Pp = L.C[sp.z];
     if (sp.y >= 0) { dS -= L.s[sp.y]; dH -= L.h[sp.y]; Pf *= L.C[sp.y]; }
     if (sp.w >= 0) { dS += L.s[sp.w]; dH += L.h[sp.w]; Pp *= L.C[sp.w]; }
-    const double dnu = p[P_DNU];
-    const double Kc = exp(dS - dH + dnu * lnPRT);
+    const double dnu = hd.dnu;
+    // k_r = k_f / K_c = k_f exp(-ln K_c)
     e.kf = kf;
-    e.kr = kf / Kc;
+    e.kr = kf * exp(-(dS - dH + dnu * lnPRT));
     e.dlnkf = dlnkf;
     e.dlnkf_dM = dlnkf_dM;
     e.dlnKc = (dH - dnu) * invT;
@@ -341,7 +363,7 @@ __device__ __forceinline__ double rhs_g(const DevMech &m, const GL &L, int r, do
     // one round overlap the arithmetic of the previous), then each species
     // lane sums its list in reaction order
     for (int j = r; j < R; j += G) {
-        const RxEval e = eval_reaction(m, L, j, x.T, x.lnT, x.invT, x.lnPRT, x.ctot, false);
+        const RxEval e = eval_reaction(m, L, j, rx_head(m, j), x.T, x.lnT, x.invT, x.lnPRT, x.ctot, false);
         double q = e.kf * e.Pf - e.kr * e.Pp;
         if (e.kind == 1) q *= e.Mc;
         L.q[j] = q;
@@ -378,7 +400,7 @@ __device__ __forceinline__ void jac_g(const DevMech &m, const GL &L, int r, doub
         const int j1 = min(R, j0 + CH);
         // per-reaction records: q, dq/dT|C, S, dense coefficient, 4 mass-action partials
         for (int j = j0 + r; j < j1; j += G) {
-            const RxEval e = eval_reaction(m, L, j, T, x.lnT, invT, x.lnPRT, x.ctot, true);
+            const RxEval e = eval_reaction(m, L, j, rx_head(m, j), T, x.lnT, invT, x.lnPRT, x.ctot, true);
             const double Rj = e.kf * e.Pf - e.kr * e.Pp;
             const double dRdT = Rj * e.dlnkf + e.kr * e.Pp * e.dlnKc;
             const double sMA = e.kind == 1 ? e.Mc : 1.0;
@@ -403,7 +425,8 @@ __device__ __forceinline__ void jac_g(const DevMech &m, const GL &L, int r, doub
         // third-body part sum_j nu_kj ctb_j of row k is added with the row pass
         if (x.isY) {
             for (; jp < jpend; ++jp) {
-                const int e = m.jl_rx[jp], j = e >> 5;
+                const JlEnt en = m.jl[jp];
+                const int e = en.e, j = e >> 5;
                 if (j >= j1) break;
                 const int4 sp = m.rsp[j];
                 const double *rc = L.rec + 8 * (j - j0);
@@ -412,7 +435,7 @@ __device__ __forceinline__ void jac_g(const DevMech &m, const GL &L, int r, doub
                 if (e & 2) dq += rc[5];
                 if (e & 4) dq += rc[6];
                 if (e & 8) dq += rc[7];
-                if (e & 16) dq += rc[3] * m.jl_em1[jp];
+                if (e & 16) dq += rc[3] * en.em1;
                 if (dq != 0.0) {
                     L.J[(1 + sp.x) * LD + r] -= dq;
                     if (sp.y >= 0) L.J[(1 + sp.y) * LD + r] -= dq;

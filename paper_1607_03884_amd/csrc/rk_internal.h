@@ -18,6 +18,20 @@ constexpr int kWave = 64;
 // Reaction parameter record (doubles per reaction).
 enum RPar { P_A = 0, P_B, P_EAR, P_A0, P_B0, P_EA0R, P_TA, P_T3, P_T1, P_T2, P_DNU, P_NPAR = 12 };
 
+// Jacobian-column list entry of species m: e = reaction << 5 | slots holding
+// m (bits 0-3: r0, r1, p0, p1) | 16 if m's efficiency there is not 1;
+// em1 = that efficiency - 1 (0 unless bit 4).  16 bytes: one load per entry.
+struct JlEnt {
+    double em1;
+    int e, pad;
+};
+
+// Third-body list entry: efficiency - 1 of species k.
+struct TbEnt {
+    double em1;
+    int k, pad;
+};
+
 // Device view of a mechanism.  Reaction/species tables are read with
 // wavefront-uniform indices, so the loads are scalar (constant cache).
 struct DevMech {
@@ -37,13 +51,11 @@ struct DevMech {
     // the mixture total of a third body: m fills a reactant or product slot,
     // or m has a non-default collision efficiency (reaction order)
     const int *jl_off;     // [K+1]
-    const int *jl_rx;      // reaction << 5 | slots holding m (bits 0-3: r0, r1, p0, p1) | 16 if efficiency != 1
-    const double *jl_em1;  // efficiency - 1 of m in that reaction (0 unless bit 4)
+    const JlEnt *jl;       // [jl_off[K]]
     // third-body row b -> the species with a non-default efficiency:
     // [M]_b = sum_k C_k + sum over the list of (efficiency - 1) C_k
     const int *tb_off;     // [n3b+1]
-    const int *tb_sp;      // species
-    const double *tb_em1;  // efficiency - 1
+    const TbEnt *tb;       // (efficiency - 1, species), 16 bytes: one load per entry
 };
 
 // Radau IIA constants and integrator parameters (computed on the host).
@@ -194,8 +206,9 @@ struct rk_mech {
     std::vector<int4> rsp;
     std::vector<int> sp_off;
     std::vector<int2> sp_rx;
-    std::vector<int> jl_off, jl_rx, tb_off, tb_sp;
-    std::vector<double> jl_em1, tb_em1;
+    std::vector<int> jl_off, tb_off;
+    std::vector<rk::JlEnt> jl;
+    std::vector<rk::TbEnt> tb;
     // device
     rk::DevMech dev{};
     void *dev_block = nullptr;
