@@ -174,7 +174,7 @@ int stats_get(rk_mech *mech, rk_stats *out, int32_t *per_state_steps, int32_t *p
  *              Newton iteration
  *              diverges twice in a row after its first accepted step continues
  *              with three to six sweeps per solve and
- *              counts in fp32_fallback; the predictor keys its bins only;
+ *              counts in fp32_fallback; predictor as for "wave";
  *              persistent work queue).
  *              RK_EINVAL outside those sizes.
  *   "binning"  number of cost bins (0..64, default 0): one source-term
@@ -195,15 +195,14 @@ int stats_get(rk_mech *mech, rk_stats *out, int32_t *per_state_steps, int32_t *p
  *              "0": forget the choices
  *   "predictor" path of a predictor file (network widths K+2 -> ... -> 3(K+1)+2,
  *              standardisation, parameters) trained for one global step size;
- *              calls with that dt and the "wave" or "mixed" variant start each
- *              state's first step from the predicted step size (rounded to dt
- *              times a power of two) and stage values and keep them only if
- *              Newton converges on that attempt, else restart the state
- *              exactly as a cold start; with "binning" (or "autotune") the
- *              bin key becomes the predicted step count.  The "block" variant
- *              uses the network for that bin key only (its states start
- *              cold).  A file for another K is refused (RK_EINVAL).  "none"
- *              removes all predictors.
+ *              calls with that dt and the "wave", "mixed" or "block" variant
+ *              start each state's first step from the predicted step size
+ *              (rounded to dt times a power of two) and stage values and keep
+ *              them only if Newton converges on that attempt, else restart the
+ *              state exactly as a cold start; with "binning" (or "autotune")
+ *              the bin key becomes the predicted step count.  A file for
+ *              another K is refused (RK_EINVAL).  "none" removes all
+ *              predictors.
  *   "predictor_use" "both" (default) | "h0" (predicted first step size only,
  *              stage values start at zero) | "z0" (predicted stage values with
  *              the default first step size) | "bins" (no warm start: the

@@ -580,9 +580,10 @@ hipError_t launch_integrator(rk_mech *m, const rk::RadauParams &p, int64_t n, co
     if (e != hipSuccess) return e;
     const int *order = nullptr;
     const double *pred = nullptr;
-    // the wavefront variants warm-start from the network and key bins by it; the
-    // block variant starts every state cold and uses the network for the bins only
-    const bool use_net = w.allow_predictor && (variant == 1 || variant == 2 || (variant == 3 && nbins > 0));
+    // the network keys the bins and, unless predictor_use is "bins", warm-starts
+    // the first step attempt (wavefront and block variants)
+    const bool use_net = w.allow_predictor && (variant == 1 || variant == 2 ||
+                                               (variant == 3 && (nbins > 0 || p.pred_use != 0)));
     rk::Predictor *pr = use_net ? predictor_for(m, p.dt) : nullptr;
     if (pr) {
         e = pr->ensure(n);
@@ -608,7 +609,8 @@ hipError_t launch_integrator(rk_mech *m, const rk::RadauParams &p, int64_t n, co
         const int64_t cap = std::max<int64_t>(1, (int64_t)m->block_blocks * gpct / 100);
         const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(n, cap));
         m->last_grid = grid;
-        return rk::launch_radau_block(m->dev, p, n, yin, yout, w.counters, w.queue, order, w.slab, grid, st);
+        return rk::launch_radau_block(m->dev, p, n, yin, yout, w.counters, w.queue, order, w.slab,
+                                      p.pred_use != 0 ? pred : nullptr, grid, st);
     }
     if (variant == 1 || variant == 2) {
         if (m->group_blocks == 0) m->group_blocks = rk::group_max_blocks(m->dev);

@@ -761,7 +761,7 @@ __global__ __launch_bounds__(BT) void radau_block_kernel(DevMech m, RadauParams 
                                                          const double *__restrict__ yin, double *__restrict__ yout,
                                                          int32_t *__restrict__ cnt, int *__restrict__ queue,
                                                          const int *__restrict__ order, double *__restrict__ slab,
-                                                         int LDJ) {
+                                                         int LDJ, const double *__restrict__ pred) {
     extern __shared__ double smem[];
     const BL L = block_lds(smem, m.R, m.n3b, m.N);
     const int t = threadIdx.x, part = t / BRP, row = t - part * BRP;
@@ -774,6 +774,8 @@ __global__ __launch_bounds__(BT) void radau_block_kernel(DevMech m, RadauParams 
     BLU<CW> F;
     double y = 0.0, h = 0.0, eta = 1.0, theta = 1.0;
     bool last = false, first = true, reject = false, jac_fresh = false, fb = false;
+    bool warm = false;     // first attempt starts from the predictor (as the wavefront kernels)
+    const int PD = 3 * m.N + 2;
     int action = ACT_JAC, status = 0, nstep = 0, nacc = 0, ndiv_row = 0, flags = 0;
     int64_t s = 0;
     auto scw = [&]() { return comp ? atol + rtol * fabs(y) : 1.0; };
@@ -817,6 +819,9 @@ __global__ __launch_bounds__(BT) void radau_block_kernel(DevMech m, RadauParams 
             flags = rp.fp64_solves ? kFlagFp32Fallback : 0;
             fb = rp.fp64_solves != 0;
             h = rp.h0;
+            // warm start: predicted first step (0: the default rule) and stage values
+            warm = pred != nullptr && rp.pred_use != 0;
+            if (warm && (rp.pred_use & 1) && pred[(size_t)s * PD + 3 * N] > 0.0) h = pred[(size_t)s * PD + 3 * N];
             last = false;
             if (1.0001 * h >= dt) { h = dt; last = true; }
             if (t == 0) { L.hist[3] = P; L.hist[4] = 0.0; }
@@ -860,7 +865,14 @@ __global__ __launch_bounds__(BT) void radau_block_kernel(DevMech m, RadauParams 
         } else {
             ++nstep;
             double Z1 = 0.0, Z2 = 0.0, Z3 = 0.0;
-            if (!first) {
+            if (first) {
+                if (warm && comp && (rp.pred_use & 2)) {
+                    const double *ps = pred + (size_t)s * PD;
+                    Z1 = ps[t];
+                    Z2 = ps[N + t];
+                    Z3 = ps[2 * N + t];
+                }
+            } else {
                 const double c1 = rp.c1, c2 = rp.c2, q = h / L.hist[2];
                 const double Zs1 = comp ? L.zs[t] : 0.0;
                 const double Zs2 = comp ? L.zs[NPB + t] : 0.0;
@@ -957,7 +969,21 @@ __global__ __launch_bounds__(BT) void radau_block_kernel(DevMech m, RadauParams 
                 W1 += dW1; W2 += dW2; W3 += dW3;
                 if (eta * dn <= kappa) { converged = true; break; }
             }
-            if (!converged) {
+            if (!converged && warm) {
+                // the prediction did not converge: restart the state exactly as a
+                // cold start (default first step, zero starting values, controller
+                // memory); J at y0 stays valid
+                bump(K_NNF, 1);
+                warm = false;
+                flags |= kFlagPredFallback;
+                h = rp.h0;
+                last = false;
+                if (1.0001 * h >= dt) { h = dt; last = true; }
+                eta = 1.0;
+                theta = 1.0;
+                if (t == 0) { L.hist[0] = h; L.hist[1] = 1e-2; L.hist[2] = h; }
+                action = ACT_LU;
+            } else if (!converged) {
                 bump(K_NNF, 1);
                 h *= 0.5;
                 reject = true;
@@ -969,6 +995,10 @@ __global__ __launch_bounds__(BT) void radau_block_kernel(DevMech m, RadauParams 
                     flags |= kFlagFp32Fallback;
                 }
             } else {
+                if (warm) {
+                    flags |= kFlagPredKept;
+                    warm = false;
+                }
                 const double invh = 1.0 / h;
                 const double dz = (rp.d[0] * Z1 + rp.d[1] * Z2 + rp.d[2] * Z3) * invh;
                 const double sc2 = comp ? atol + rtol * fmax(fabs(y), fabs(y + Z3)) : 1.0;
@@ -1128,12 +1158,13 @@ int block_max_blocks(const DevMech &m) {
 }
 
 hipError_t launch_radau_block(const DevMech &m, const RadauParams &p, int64_t n, const double *yin, double *yout,
-                              int32_t *counters, int *queue, const int *order, double *slab, int grid, hipStream_t st) {
+                              int32_t *counters, int *queue, const int *order, double *slab, const double *pred,
+                              int grid, hipStream_t st) {
     if (n == 0) return hipSuccess;
     if (!block_supported(m.N) || grid < 1) return hipErrorInvalidValue;
     hipLaunchKernelGGL(reset_block_queue_kernel, dim3(1), dim3(64), 0, st, queue);
     hipLaunchKernelGGL((radau_block_kernel<kCW>), dim3(grid), dim3(BT), block_lds_bytes(m), st, m, p, n, yin, yout,
-                       counters, queue, order, slab, block_ldj(m.N));
+                       counters, queue, order, slab, block_ldj(m.N), pred);
     return hipGetLastError();
 }
 

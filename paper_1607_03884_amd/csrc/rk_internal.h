@@ -140,7 +140,8 @@ size_t block_lds_bytes(const DevMech &m);
 size_t block_slab_doubles(int N, int grid);
 int block_max_blocks(const DevMech &m);
 hipError_t launch_radau_block(const DevMech &m, const RadauParams &p, int64_t n, const double *yin, double *yout,
-                              int32_t *counters, int *queue, const int *order, double *slab, int grid, hipStream_t st);
+                              int32_t *counters, int *queue, const int *order, double *slab, const double *pred,
+                              int grid, hipStream_t st);
 size_t group_lds_bytes(const DevMech &m);   // per block
 
 // Device buffers of one integration call (rk_api.cpp): the handle's

@@ -270,3 +270,42 @@ def test_m150_block_costliest_states(torch_dev, g150, o150):
     print(f"M150 costliest: kernel {st['kernel_ms']:.1f} ms, max steps {steps.max()}, "
           f"max rel err T {eT:.2e} Y {eY:.2e}, identical step counts {same:.3f}, fp32_fallback {st['fp32_fallback']}")
     assert eT <= 1e-5 and eY <= 1e-5
+
+
+def test_m150_block_warm_start(torch_dev, g150, o150):
+    """The block kernel started from the 150-species network's predicted first
+    step and stage values (kept only when Newton converges on that attempt)
+    against the oracle started from the same prediction, which decodes the
+    committed predictor file itself; a cold restart for every state whose
+    warm attempt fails, as in the oracle."""
+    import os
+    from oracle import predict as opred
+    from paper_1607_03884_amd import predictor
+    path = predictor.path_for("M150", 1e-4)
+    if not os.path.exists(path):
+        pytest.skip("no M150 predictor file")
+    torch, _ = torch_dev
+    banner("M150 block warm start")
+    rows = configs.states_for(configs.WORKLOADS["cfg4"], 192)
+    g150.set_option("variant", "block")
+    g150.set_option("predictor", path)
+    g150.set_option("predictor_use", "both")
+    g150.set_option("binning", "16")
+    got = g150.integrate(_dev(torch_dev, rows), 1e-4).cpu().numpy().T
+    st = g150.stats(per_state=True)
+    g150.set_option("binning", "0")
+    g150.set_option("predictor", "none")
+    g150.set_option("variant", "auto")
+    pr = opred.load(path)
+    h, z, _ = opred.warm_start(pr, rows, configs.ATOL, configs.RTOL, 1e-4)
+    ref, res = o150.integrate_warm(rows, 1e-4, h, z)
+    assert np.all(res["status"] == 0) and np.all(st["per_state_status"] == 0)
+    eT, eY = integration_errors(got, ref, K)
+    same = np.mean(st["per_state_steps"] == res["nstep"])
+    kept = int(np.sum(res["warm"] == 1))
+    print(f"M150 block warm: kept {st['predictor_kept']} (oracle {kept}), restarted {st['predictor_fallback']}; "
+          f"vs same-start oracle T {eT:.2e} Y {eY:.2e}, identical step counts {same:.3f}, "
+          f"steps/state {st['steps'] / len(rows):.1f} (oracle {res['nstep'].mean():.1f})")
+    assert st["predictor_kept"] + st["predictor_fallback"] == len(rows)
+    assert abs(st["predictor_kept"] - kept) <= 2
+    assert eT <= 1e-5 and eY <= 1e-5
