@@ -193,6 +193,7 @@ int upload(rk_mech *m, const std::vector<Rx> &rx, const std::vector<double> &alo
     m->rsp.assign(R, int4{-1, -1, -1, -1});
     m->rinfo.assign(R, 0);
     m->rpar.assign((size_t)R * rk::P_NPAR, 0.0);
+    m->rhead.assign(std::max(R, 1), double4{0.0, 0.0, 0.0, 0.0});
     m->eff.clear();
     m->n3b = 0;
     for (int j = 0; j < R; ++j) {
@@ -210,6 +211,7 @@ int upload(rk_mech *m, const std::vector<Rx> &rx, const std::vector<double> &alo
         p[rk::P_A0] = x.A0; p[rk::P_B0] = x.b0; p[rk::P_EA0R] = x.Ea0 / rk::kRu;
         p[rk::P_TA] = x.troe[0]; p[rk::P_T3] = x.troe[1]; p[rk::P_T1] = x.troe[2]; p[rk::P_T2] = x.troe[3];
         p[rk::P_DNU] = (double)(x.np - x.nr);
+        m->rhead[j] = double4{p[rk::P_A], p[rk::P_B], p[rk::P_EAR], p[rk::P_DNU]};
     }
     if (m->eff.empty()) m->eff.push_back(0.0);
     // species -> (reaction, net nu) lists
@@ -270,7 +272,8 @@ int upload(rk_mech *m, const std::vector<Rx> &rx, const std::vector<double> &alo
         {m->eff.data(), m->eff.size() * sizeof(double), 0},
         {m->sp_off.data(), m->sp_off.size() * sizeof(int), 0}, {m->sp_rx.data(), m->sp_rx.size() * sizeof(int2), 0},
         {m->jl_off.data(), m->jl_off.size() * sizeof(int), 0}, {m->jl.data(), m->jl.size() * sizeof(rk::JlEnt), 0},
-        {m->tb_off.data(), m->tb_off.size() * sizeof(int), 0}, {m->tb.data(), m->tb.size() * sizeof(rk::TbEnt), 0}};
+        {m->tb_off.data(), m->tb_off.size() * sizeof(int), 0}, {m->tb.data(), m->tb.size() * sizeof(rk::TbEnt), 0},
+        {m->rhead.data(), m->rhead.size() * sizeof(double4), 0}};
     size_t total = 0;
     for (Part &p : parts) { p.off = total; total += (p.bytes + 255) / 256 * 256; }
     std::vector<char> host(total, 0);
@@ -299,6 +302,7 @@ int upload(rk_mech *m, const std::vector<Rx> &rx, const std::vector<double> &alo
     d.jl = reinterpret_cast<const rk::JlEnt *>(b + parts[11].off);
     d.tb_off = reinterpret_cast<const int *>(b + parts[12].off);
     d.tb = reinterpret_cast<const rk::TbEnt *>(b + parts[13].off);
+    d.rhead = reinterpret_cast<const double4 *>(b + parts[14].off);
     e = hipEventCreate(&m->ev0);
     if (e == hipSuccess) e = hipEventCreate(&m->ev1);
     if (e != hipSuccess) return hip_fail(e, "hipEventCreate");

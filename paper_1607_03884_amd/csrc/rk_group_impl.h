@@ -233,8 +233,8 @@ struct RxHead {
 };
 
 __device__ __forceinline__ RxHead rx_head(const DevMech &m, int j) {
-    const double *p = m.rpar + (size_t)j * P_NPAR;
-    return RxHead{m.rsp[j], m.rinfo[j], p[P_A], p[P_B], p[P_EAR], p[P_DNU]};
+    const double4 hp = m.rhead[j];     // 32 bytes: a third of a full parameter record
+    return RxHead{m.rsp[j], m.rinfo[j], hp.x, hp.y, hp.z, hp.w};
 }
 
 __device__ __forceinline__ RxEval eval_reaction(const DevMech &m, const GL &L, int j, const RxHead &hd, double T,

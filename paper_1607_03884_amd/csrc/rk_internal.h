@@ -44,6 +44,7 @@ struct DevMech {
     const int4 *rsp;       // [R]  reactant slots r0, r1, product slots p0, p1 (-1 = empty)
     const int *rinfo;      // [R]  kind | nr << 4 | np << 8 | (third-body row + 1) << 12
     const double *rpar;    // [R][P_NPAR]
+    const double4 *rhead;  // [R]: A, b, E_a/R, sum of nu (the parameters every reaction reads)
     const double *eff;     // [n3b][K] collision efficiencies
     const int *sp_off;     // [K+1] species -> reaction list offsets
     const int2 *sp_rx;     // [sp_off[K]] (reaction, net stoichiometric coefficient)
@@ -203,6 +204,7 @@ struct rk_mech {
     std::string name;
     // host copies
     std::vector<double> W, Tmid, thermo, rpar, eff;
+    std::vector<double4> rhead;
     std::vector<int> rinfo, comp;
     std::vector<int4> rsp;
     std::vector<int> sp_off;
