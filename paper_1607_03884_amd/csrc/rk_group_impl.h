@@ -371,9 +371,18 @@ __device__ __forceinline__ double rhs_g(const DevMech &m, const GL &L, int r, do
     sync_wave();
     double wdot = 0.0;
     const int iend = x.isY ? L.spoff[x.k + 1] : 0;
-    for (int i = x.isY ? L.spoff[x.k] : 0; i < iend; ++i) {
-        const int e = L.sprx[i];
-        wdot += ((e & 15) - 8) * L.q[e >> 4];
+    // four list entries per round: their loads (entry, then rate) overlap;
+    // the sum keeps the list order
+    for (int i = x.isY ? L.spoff[x.k] : 0; i < iend; i += 4) {
+        int ev[4];
+        double qv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) ev[u] = i + u < iend ? L.sprx[i + u] : 8;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) qv[u] = L.q[ev[u] >> 4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (i + u < iend) wdot += ((ev[u] & 15) - 8) * qv[u];
     }
     sync_wave();
     const double hw = gsum<G>(x.isY ? th.h * wdot : 0.0);
