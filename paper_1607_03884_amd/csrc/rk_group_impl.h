@@ -453,15 +453,31 @@ __device__ __forceinline__ void jac_g(const DevMech &m, const GL &L, int r, doub
                 }
             }
         }
-        // species sums over this chunk, in reaction order
-        for (; i < iend; ++i) {
-            const int e = L.sprx[i], jr = e >> 4, nu = (e & 15) - 8;
-            if (jr >= j1) break;
-            const double *rc = L.rec + 8 * (jr - j0);
-            wdot += nu * rc[0];
-            dwdT += nu * rc[1];
-            sS += nu * rc[2];
-            ck += nu * rc[3];       // third-body coefficient (0 for elementary reactions)
+        // species sums over this chunk, in reaction order (four list entries
+        // per round so their loads overlap)
+        for (bool more = true; more && i < iend;) {
+            int ev[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) ev[u] = i + u < iend ? L.sprx[i + u] : (R << 4);
+            double4 rv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int jr = ev[u] >> 4;
+                const double *rc = L.rec + 8 * (jr < j1 ? jr - j0 : 0);
+                rv[u] = double4{rc[0], rc[1], rc[2], rc[3]};
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int jr = ev[u] >> 4, nu = (ev[u] & 15) - 8;
+                more = more && jr < j1;
+                if (more) {
+                    wdot += nu * rv[u].x;
+                    dwdT += nu * rv[u].y;
+                    sS += nu * rv[u].z;
+                    ck += nu * rv[u].w;     // third-body coefficient (0 for elementary reactions)
+                    ++i;
+                }
+            }
         }
         sync_wave();
     }
