@@ -269,10 +269,19 @@ __device__ __forceinline__ double rhs_b(const DevMech &m, const BL &L, int t, do
     __syncthreads();
     double wdot = 0.0;
     if (x.isY) {
+        // eight list entries per round: their loads (entry, then rate)
+        // overlap; the sum keeps the list order
         const int i1 = m.sp_off[x.k + 1];
-        for (int i = m.sp_off[x.k]; i < i1; ++i) {
-            const int2 e = m.sp_rx[i];
-            wdot += e.y * L.q[e.x];
+        for (int i = m.sp_off[x.k]; i < i1; i += 8) {
+            int2 ev[8];
+            double qv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) ev[u] = i + u < i1 ? m.sp_rx[i + u] : int2{0, 0};
+#pragma unroll
+            for (int u = 0; u < 8; ++u) qv[u] = L.q[ev[u].x];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (i + u < i1) wdot += ev[u].y * qv[u];
         }
     }
     double hw = x.isY ? th.h * wdot : 0.0, cpm = x.isY ? x.Y * th.cp * x.invW : 0.0;
@@ -362,14 +371,28 @@ __device__ __forceinline__ void jac_b(const DevMech &m, const BL &L, int t, doub
                 }
             }
         }
-        for (; i < iend; ++i) {
-            const int2 e = m.sp_rx[i];
-            if (e.x >= j1) break;
-            const double *rc = rec + 8 * (e.x - j0);
-            wdot += e.y * rc[0];
-            dwdT += e.y * rc[1];
-            sS += e.y * rc[2];
-            ck += e.y * rc[3];      // third-body coefficient (0 for elementary reactions)
+        // (four list entries per round so their loads overlap; list order kept)
+        for (bool more = true; more && i < iend;) {
+            int2 ev[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) ev[u] = i + u < iend ? m.sp_rx[i + u] : int2{R, 0};
+            double4 rv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const double *rc = rec + 8 * (ev[u].x < j1 ? ev[u].x - j0 : 0);
+                rv[u] = double4{rc[0], rc[1], rc[2], rc[3]};
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                more = more && ev[u].x < j1;
+                if (more) {
+                    wdot += ev[u].y * rv[u].x;
+                    dwdT += ev[u].y * rv[u].y;
+                    sS += ev[u].y * rv[u].z;
+                    ck += ev[u].y * rv[u].w;    // third-body coefficient (0 for elementary reactions)
+                    ++i;
+                }
+            }
         }
         __syncthreads();
     }
