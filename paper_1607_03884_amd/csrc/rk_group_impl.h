@@ -92,6 +92,21 @@ __device__ __forceinline__ uint64_t gmaxu(uint64_t v) {
 }
 
 template <int G>
+__device__ __forceinline__ uint32_t gmaxu32(uint32_t v) {
+    auto mx = [](uint32_t a, uint32_t b) { return a > b ? a : b; };
+    v = mx(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kRowMirror, 0xF, 0xF, false));
+    v = mx(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kRowHalfMirror, 0xF, 0xF, false));
+    v = mx(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kQuadXor2, 0xF, 0xF, false));
+    v = mx(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kQuadXor1, 0xF, 0xF, false));
+    if constexpr (G == 64) {
+        const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)v, 0), b = (uint32_t)__builtin_amdgcn_readlane((int)v, 16);
+        const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)v, 32), d = (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
+        v = mx(mx(a, b), mx(c, d));
+    }
+    return v;
+}
+
+template <int G>
 __device__ __forceinline__ double gb(double v, int src) { return __shfl(v, src, G); }
 template <int G>
 __device__ __forceinline__ float gb(float v, int src) { return __shfl(v, src, G); }
@@ -106,6 +121,14 @@ __device__ __forceinline__ int gpivot(double mag, bool used, int lane) {
     constexpr uint64_t kMask = G - 1;
     const uint64_t key = used ? 0ull : ((__builtin_bit_cast(uint64_t, mag) & ~kMask) | (uint64_t)(kMask - lane));
     return (int)kMask - (int)(gmaxu<G>(key) & kMask);
+}
+// The same on FP32 magnitudes (FP32 factors): 32-bit keys, half the moves;
+// magnitudes within 2^-(23 - log2 G) of each other count as equal.
+template <int G>
+__device__ __forceinline__ int gpivot(float mag, bool used, int lane) {
+    constexpr uint32_t kMask = G - 1;
+    const uint32_t key = used ? 0u : ((__builtin_bit_cast(uint32_t, mag) & ~kMask) | (kMask - (uint32_t)lane));
+    return (int)kMask - (int)(gmaxu32<G>(key) & kMask);
 }
 
 // LDS slice of one group (doubles).  J is row-major with an odd leading
@@ -608,7 +631,7 @@ __device__ __forceinline__ void factor_real(LUR<S, NC> &F, const GL &L, int r, i
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
         if (k < N) {
-            const int p = gpivot<G>(fabs((double)F.a[k]), used, r);
+            const int p = gpivot<G>(fabs(F.a[k]), used, r);
             if (r == k) src = p;
             if constexpr (G == 64) {
                 if (r == p) {
@@ -657,7 +680,7 @@ __device__ __forceinline__ void factor_cplx(LUC<S, NC> &F, const GL &L, int r, i
     for (int k = 0; k < NC; ++k) {
         if (k < N) {
             const double mr = F.re[k], mi = F.im[k];
-            const int p = gpivot<G>(mr * mr + mi * mi, used, r);
+            const int p = gpivot<G>((S)(mr * mr + mi * mi), used, r);
             if (r == k) src = p;
             if (r == p) {
                 used = true;
