@@ -309,3 +309,41 @@ def test_m150_block_warm_start(torch_dev, g150, o150):
     assert st["predictor_kept"] + st["predictor_fallback"] == len(rows)
     assert abs(st["predictor_kept"] - kept) <= 2
     assert eT <= 1e-5 and eY <= 1e-5
+
+
+def test_m150_block_poisoned_predictor(torch_dev, g150, o150, tmp_path):
+    """A predictor with garbage outputs (huge stage values, tiny first steps)
+    on the block kernel: Newton rejects the predicted stage values, the state
+    restarts exactly as a cold start (bitwise the cold result), and every
+    result meets the bar against the cold oracle."""
+    import os
+    from paper_1607_03884_amd import predictor
+    torch, _ = torch_dev
+    banner("M150 block poisoned predictor")
+    N, dt = K + 1, 1e-4
+    dims = [K + 2, 16, 3 * N + 2]
+    rng = np.random.default_rng(6)
+    nparam = sum(dims[i] * dims[i + 1] + dims[i + 1] for i in range(len(dims) - 1))
+    params = rng.standard_normal(nparam) * 3.0
+    out_shift = np.concatenate([np.full(3 * N, 30.0), [-4.0, 1.0]])
+    path = os.path.join(str(tmp_path), "poison150.rkp")
+    predictor.write(path, "M150", K, dt, dims, np.zeros(K + 2), np.ones(K + 2), out_shift, np.full(3 * N + 2, 5.0),
+                    params)
+    rows = configs.states_for(configs.WORKLOADS["cfg4"], 67)
+    g150.set_option("variant", "block")
+    cold = g150.integrate(_dev(torch_dev, rows), dt).cpu().numpy().T
+    g150.set_option("predictor", path)
+    g150.set_option("predictor_use", "both")
+    got = g150.integrate(_dev(torch_dev, rows), dt).cpu().numpy().T
+    st = g150.stats(per_state=True)
+    g150.set_option("predictor", "none")
+    g150.set_option("variant", "auto")
+    ref, res = o150.integrate(rows, dt)
+    eT, eY = integration_errors(got, ref, K)
+    same = int(np.sum(np.all(got == cold, axis=1)))
+    print(f"M150 block poisoned: restarted {st['predictor_fallback']}, kept {st['predictor_kept']}, "
+          f"bitwise cold {same}; vs cold oracle T {eT:.2e} Y {eY:.2e}")
+    assert np.all(st["per_state_status"] == 0)
+    assert st["predictor_fallback"] >= 0.9 * len(rows)
+    assert same >= st["predictor_fallback"]
+    assert eT <= 1e-5 and eY <= 1e-5
