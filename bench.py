@@ -13,7 +13,7 @@ Forms (same library, same inputs):
                  (variant "mixed"), persistent queue ordered by autotuned bins
                  of the MLP's predicted step counts, cold starts (the network
                  orders the queue and nothing else, so results are bitwise those
-                 of the mixed variant and are judged against the cold oracle)
+                 of the mixed variant and are compared with the cold oracle)
   plain          FP64 factors, one 16-lane group (N <= 16) or wavefront per
                  state, persistent queue in input order, no predictor
   binned         plain + autotuned proxy-key cost bins
@@ -21,15 +21,17 @@ Forms (same library, same inputs):
   learned_fp64   the learned form with FP64 factors
   learned_warm   the learned form plus the predicted first step size and
                  stage values as warm start (a different step sequence:
-                 judged against the oracle started from the same prediction,
+                 compared with the oracle started from the same prediction,
                  its deviation from the cold oracle reported)
   lane           one state per lane (the paper's per-thread pattern)
   block          one 512-lane block per state, FP32 factors, 16 proxy cost
                  bins (N = 57..153; the cooperative form for 150 species)
-  block_fp64     block with FP64-accurate solves (three refinement sweeps
-                 per solve from the first step)
+  block_fp64     block with FP64-accurate solves (three to six refinement
+                 sweeps per solve from the first step)
   block_learned  block with its queue binned by the MLP's predicted step
                  counts (cold starts)
+  block_learned_warm  block_learned plus the predicted first step size and
+                 stage values as warm start (as learned_warm)
   rodas3         the Rosenbrock method Rodas3 on the wavefront kernels (FP64,
                  autotuned proxy bins): the semi-implicit alternative the
                  paper recommends; it solves the same ODE to the same
@@ -160,7 +162,7 @@ def main() -> int:
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: states are independent and the multi-GPU path "
-              "(sharding states across GPUs) is not part of this build; run with --gpus 1.", file=sys.stderr)
+              "(sharding states across GPUs) is not implemented; run with --gpus 1.", file=sys.stderr)
         return 2
 
     import numpy as np
