@@ -259,6 +259,13 @@ int upload(rk_mech *m, const std::vector<Rx> &rx, const std::vector<double> &alo
     }
     m->tb_off[m->n3b] = (int)m->tb.size();
     if (m->tb.empty()) m->tb.push_back(rk::TbEnt{0.0, 0, 0});
+    // per reaction: its third-body row's range in tb (read with the reaction's
+    // other table entries, so the row offset is not a dependent load)
+    m->tbr.assign(std::max(R, 1), int2{0, 0});
+    for (int j = 0; j < R; ++j) {
+        const int row = (m->rinfo[j] >> 12) - 1;
+        if ((m->rinfo[j] & 15) != 0 && row >= 0) m->tbr[j] = int2{m->tb_off[row], m->tb_off[row + 1]};
+    }
     std::vector<double> invW(K);
     for (int k = 0; k < K; ++k) invW[k] = 1.0 / m->W[k];
 
@@ -273,7 +280,8 @@ int upload(rk_mech *m, const std::vector<Rx> &rx, const std::vector<double> &alo
         {m->sp_off.data(), m->sp_off.size() * sizeof(int), 0}, {m->sp_rx.data(), m->sp_rx.size() * sizeof(int2), 0},
         {m->jl_off.data(), m->jl_off.size() * sizeof(int), 0}, {m->jl.data(), m->jl.size() * sizeof(rk::JlEnt), 0},
         {m->tb_off.data(), m->tb_off.size() * sizeof(int), 0}, {m->tb.data(), m->tb.size() * sizeof(rk::TbEnt), 0},
-        {m->rhead.data(), m->rhead.size() * sizeof(double4), 0}};
+        {m->rhead.data(), m->rhead.size() * sizeof(double4), 0},
+        {m->tbr.data(), m->tbr.size() * sizeof(int2), 0}};
     size_t total = 0;
     for (Part &p : parts) { p.off = total; total += (p.bytes + 255) / 256 * 256; }
     std::vector<char> host(total, 0);
@@ -303,6 +311,7 @@ int upload(rk_mech *m, const std::vector<Rx> &rx, const std::vector<double> &alo
     d.tb_off = reinterpret_cast<const int *>(b + parts[12].off);
     d.tb = reinterpret_cast<const rk::TbEnt *>(b + parts[13].off);
     d.rhead = reinterpret_cast<const double4 *>(b + parts[14].off);
+    d.tbr = reinterpret_cast<const int2 *>(b + parts[15].off);
     e = hipEventCreate(&m->ev0);
     if (e == hipSuccess) e = hipEventCreate(&m->ev1);
     if (e != hipSuccess) return hip_fail(e, "hipEventCreate");

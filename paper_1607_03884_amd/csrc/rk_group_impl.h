@@ -252,12 +252,13 @@ struct RxEval {
 struct RxHead {
     int4 sp;
     int info;
+    int2 tbr;      // third-body row's range in the sparse efficiency entries
     double A, B, EaR, dnu;
 };
 
 __device__ __forceinline__ RxHead rx_head(const DevMech &m, int j) {
     const double4 hp = m.rhead[j];     // 32 bytes: a third of a full parameter record
-    return RxHead{m.rsp[j], m.rinfo[j], hp.x, hp.y, hp.z, hp.w};
+    return RxHead{m.rsp[j], m.rinfo[j], m.tbr[j], hp.x, hp.y, hp.z, hp.w};
 }
 
 __device__ __forceinline__ RxEval eval_reaction(const DevMech &m, const GL &L, int j, const RxHead &hd, double T,
@@ -284,8 +285,8 @@ __device__ __forceinline__ RxEval eval_reaction(const DevMech &m, const GL &L, i
             // efficiencies of (eff_k - 1) C_k
             // (entries fetched eight at a time so their loads overlap)
             Mc = ctot;
-            const int p1 = m.tb_off[b + 1];
-            for (int p = m.tb_off[b]; p < p1; p += 8) {
+            const int p1 = hd.tbr.y;
+            for (int p = hd.tbr.x; p < p1; p += 8) {
                 TbEnt te[8];
 #pragma unroll
                 for (int u = 0; u < 8; ++u) te[u] = p + u < p1 ? m.tb[p + u] : TbEnt{0.0, 0, 0};

@@ -57,6 +57,7 @@ struct DevMech {
     // [M]_b = sum_k C_k + sum over the list of (efficiency - 1) C_k
     const int *tb_off;     // [n3b+1]
     const TbEnt *tb;       // (efficiency - 1, species), 16 bytes: one load per entry
+    const int2 *tbr;       // [R]: a reaction's range in tb (empty for elementary reactions)
 };
 
 // Radau IIA constants and integrator parameters (computed on the host).
@@ -212,6 +213,7 @@ struct rk_mech {
     std::vector<int> jl_off, tb_off;
     std::vector<rk::JlEnt> jl;
     std::vector<rk::TbEnt> tb;
+    std::vector<int2> tbr;
     // device
     rk::DevMech dev{};
     void *dev_block = nullptr;
