@@ -34,7 +34,9 @@
 // last increment (the exact solve would conserve it to rounding).
 //
 // Work distribution: a persistent grid whose blocks pull states from a device
-// queue, optionally in a caller-supplied order.
+// queue, optionally in a caller-supplied order.  A state's first step attempt
+// may start from the predictor's step size and stage values, kept only if
+// Newton converges (else the state restarts cold), as in the wavefront kernels.
 #include <hip/hip_runtime.h>
 #include <algorithm>
 #include <cmath>
