@@ -347,3 +347,38 @@ def test_m150_block_poisoned_predictor(torch_dev, g150, o150, tmp_path):
     assert st["predictor_fallback"] >= 0.9 * len(rows)
     assert same >= st["predictor_fallback"]
     assert eT <= 1e-5 and eY <= 1e-5
+
+
+def test_m150_block_options_and_step_limit(torch_dev, g150, o150):
+    """The block kernel's Newton and step-size options (kmax 4, kappa 0.01,
+    first step 1e-9 s) against the oracle with the same options, and the
+    step-attempt limit: with nmax = 3 every state stops with STEP_LIMIT and
+    keeps its last accepted solution, as the oracle does."""
+    import oracle
+    torch, _ = torch_dev
+    banner("M150 block options kmax=4 kappa=0.01 h0=1e-9, nmax=3")
+    rows = configs.states_for(configs.WORKLOADS["cfg4"], 40)
+    g150.set_option("variant", "block")
+    for k, v in (("kmax", "4"), ("kappa", "0.01"), ("h0", "1e-9")):
+        g150.set_option(k, v)
+    got = g150.integrate(_dev(torch_dev, rows), 1e-6).cpu().numpy().T
+    st = g150.stats(per_state=True)
+    for k, v in (("kmax", "7"), ("kappa", "0"), ("h0", "0")):
+        g150.set_option(k, v)
+    ref, res = o150.integrate(rows, 1e-6, opts=oracle.default_opts(kmax=4, kappa=0.01, h0=1e-9))
+    eT, eY = integration_errors(got, ref, K)
+    same = np.mean(st["per_state_steps"] == res["nstep"])
+    print(f"M150 block options: T {eT:.2e} Y {eY:.2e}, identical step counts {same:.3f}")
+    assert np.all(st["per_state_status"] == 0) and np.all(res["status"] == 0)
+    assert eT <= 1e-5 and eY <= 1e-5 and same >= 0.95
+    g150.set_option("nmax", "3")
+    got = g150.integrate(_dev(torch_dev, rows), 1e-4).cpu().numpy().T
+    st = g150.stats(per_state=True)
+    g150.set_option("nmax", "100000")
+    g150.set_option("variant", "auto")
+    ref, res = o150.integrate(rows, 1e-4, opts=oracle.default_opts(nmax=3))
+    print(f"M150 block nmax=3: status {np.bincount(st['per_state_status'])}, oracle {np.bincount(res['status'])}")
+    assert np.all(st["per_state_status"] == 1) and np.all(res["status"] == 1)
+    assert np.array_equal(st["per_state_steps"], res["nstep"])
+    eT, eY = integration_errors(got, ref, K)
+    assert eT <= 1e-5 and eY <= 1e-5
