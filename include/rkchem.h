@@ -111,8 +111,10 @@ int mech_dims(const rk_mech *mech, int32_t *K, int32_t *R);
  *       returns after enqueueing; results are ready when the stream is.
  * One call in flight per handle: a second call on the same handle must not
  * start before the first one's stream work has been ordered before it.
- * Returns RK_EINVAL for dt <= 0, atol < 0, rtol <= 0, n_states < 0 or a NULL
- * pointer with n_states > 0; RK_ENOMEM / RK_EHIP on runtime failures.
+ * Returns RK_EINVAL for dt <= 0 or not finite, atol < 0, rtol <= 0,
+ * n_states < 0, a NULL or host-memory state array with n_states > 0, or a
+ * variant, method or Jacobian option (radau_set_option) that does not fit the
+ * mechanism or each other; RK_ENOMEM / RK_EHIP on runtime failures.
  * Failures of individual states go to their status (stats_get); a failed
  * state keeps its last accepted solution in d_y_out. */
 int radau_integrate(rk_mech *mech, int64_t n_states, double dt, const double *d_y_in, double *d_y_out,
@@ -166,8 +168,9 @@ int stats_get(rk_mech *mech, rk_stats *out, int32_t *per_state_steps, int32_t *p
  *              2000: a block of 512 lanes
  *              cooperates on one state, the per-block pattern for large
  *              mechanisms (Sec. 1.2, Sec. 4); iteration matrices equilibrated
- *              and factored in FP32 in registers, three lanes per row, J in
- *              FP64 in device memory; every solve refined against the FP64
+ *              and factored in FP32 (the complex one in registers, three
+ *              lanes per row; the real one in LDS), J in FP64 in device
+ *              memory; every solve refined against the FP64
  *              matrices until the last correction is below 1e-8 in the error
  *              weights (one to four sweeps; a correction larger than the
  *              one before it ends the sweeps unapplied); a state whose
