@@ -56,12 +56,15 @@ if ROOT not in sys.path:
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CUs x 64 FP64 FMA/clk x 2 flops x 2.4 GHz
 
-# source files whose text decides each kernel's code (counter summaries carry
-# their hash and are ignored once the kernel source changes)
-KERNEL_SOURCES = {"radau_group_kernel16": ["rk_group_impl.h", "rk_group16.hip"],
-                  "radau_group_kernel64": ["rk_group_impl.h", "rk_group64.hip"],
-                  "radau_block_kernel": ["rk_block.hip", "rk_group_impl.h"],
-                  "radau_lane_kernel": ["rk_kernels.hip"]}
+# source files whose text decides each kernel's code, launch shape and table
+# layouts (counter summaries carry their hash and are ignored once any of them
+# changes): the kernel's own sources, the shared device structures, and the
+# host code that builds the device tables and launches it
+_COMMON = ["rk_internal.h", "rk_api.cpp"]
+KERNEL_SOURCES = {"radau_group_kernel16": ["rk_group_impl.h", "rk_group16.hip", "rk_group.hip"] + _COMMON,
+                  "radau_group_kernel64": ["rk_group_impl.h", "rk_group64.hip", "rk_group.hip"] + _COMMON,
+                  "radau_block_kernel": ["rk_block.hip", "rk_group_impl.h"] + _COMMON,
+                  "radau_lane_kernel": ["rk_kernels.hip"] + _COMMON}
 
 FORMS = {
     "learned": dict(variant="mixed", binning=0, autotune=1, predictor="bins"),
